@@ -1,0 +1,238 @@
+"""CPU FP64 oracle for the SPGM near-field MIMO projector (arXiv 2509.00774).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the package smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with the
+HIP path: the arithmetic lives in ``spgm_oracle.c`` (plain double precision, OpenMP
+over independent rows or voxels) and this module only marshals numpy arrays.
+
+Functions and the passage each one follows:
+
+* :meth:`Oracle.entry`, :meth:`Oracle.dense`            -- observation-matrix entry (Sec. II, Eq. 2)
+* :meth:`Oracle.forward`, :meth:`Oracle.forward_sparse`  -- y_B = A_B s (Sec. II, Eq. 1)
+* :meth:`Oracle.adjoint`                                 -- A_B^H r (conjugate transpose of Eq. 1)
+* :func:`prox_l1`                                        -- prox of alpha*||.||_1 used in Eq. 5
+* :meth:`Oracle.gradient`                                -- minibatch gradient (Sec. IV-A, Eq. 6)
+* :meth:`Oracle.step`, :meth:`Oracle.solve`              -- SPGM / PGM iteration (Sec. IV, Eq. 5)
+* :meth:`Oracle.lambda_max`                              -- smallest lambda with zero minimiser of Eq. 3 with Eq. 4
+* :meth:`Oracle.lipschitz`                               -- power iteration on A_B^H A_B / B (step-size choice)
+* :func:`nmse`, :func:`psnr_magnitude`                   -- error metrics (Sec. V, PSNR over normalised magnitudes)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import ensure_oracle
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+
+class _Geometry(C.Structure):
+    _fields_ = [
+        ("n_tx", C.c_int32), ("n_rx", C.c_int32), ("n_freq", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("tx_xyz", _dp), ("rx_xyz", _dp), ("freq_hz", _dp), ("pulse", _dp),
+        ("centre", C.c_double * 3), ("pitch", C.c_double * 3), ("c", C.c_double),
+    ]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        lib = C.CDLL(ensure_oracle())
+        g = C.POINTER(_Geometry)
+        sig = {
+            "ora_num_threads": (C.c_int, []),
+            "ora_num_rows": (C.c_int64, [g]),
+            "ora_num_voxels": (C.c_int64, [g]),
+            "ora_voxel_position": (None, [g, C.c_int64, _dp]),
+            "ora_entry": (None, [g, C.c_int64, C.c_int64, _dp]),
+            "ora_dense": (None, [g, _ip, C.c_int32, _dp]),
+            "ora_forward": (None, [g, _ip, C.c_int32, _dp, _dp]),
+            "ora_forward_sparse": (None, [g, _ip, C.c_int32, _lp, _dp, C.c_int64, _dp]),
+            "ora_adjoint": (None, [g, _ip, C.c_int32, _dp, _dp]),
+            "ora_prox_l1": (None, [_dp, C.c_int64, C.c_double]),
+            "ora_stochastic_gradient": (None, [g, _ip, C.c_int32, _dp, _dp, _dp]),
+            "ora_step": (None, [g, _ip, C.c_int32, _dp, _dp, C.c_double, C.c_double]),
+            "ora_solve": (None, [g, _ip, C.c_int32, C.c_int32, _dp, _dp, C.c_double, C.c_double]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses (``OMP_NUM_THREADS`` or the host's core count)."""
+    return int(_lib().ora_num_threads())
+
+
+def _c128(a) -> np.ndarray:
+    """Complex array -> contiguous complex128 (interleaved re, im doubles)."""
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+class Oracle:
+    """FP64 reference for one imaging geometry.
+
+    ``geom`` is a mapping with keys ``tx`` (T x 3), ``rx`` (R x 3), ``freq`` (F,),
+    ``pulse`` (F complex, or None for p = 1), ``grid`` (nx, ny, nz), ``centre`` (3,),
+    ``pitch`` (3,) and ``c`` -- the same fields the C-ABI plan takes.
+    """
+
+    def __init__(self, geom):
+        self._keep = []
+        tx = _f64(geom["tx"]).reshape(-1, 3)
+        rx = _f64(geom["rx"]).reshape(-1, 3)
+        fr = _f64(geom["freq"]).reshape(-1)
+        pulse = geom.get("pulse")
+        pl = None if pulse is None else _f64(np.stack([np.real(pulse), np.imag(pulse)], -1).reshape(-1))
+        self._keep += [tx, rx, fr, pl]
+        nx, ny, nz = (int(v) for v in geom["grid"])
+        g = _Geometry()
+        g.n_tx, g.n_rx, g.n_freq = tx.shape[0], rx.shape[0], fr.shape[0]
+        g.nx, g.ny, g.nz = nx, ny, nz
+        g.tx_xyz, g.rx_xyz, g.freq_hz = _ptr(tx), _ptr(rx), _ptr(fr)
+        g.pulse = _ptr(pl) if pl is not None else _dp()
+        g.centre = (C.c_double * 3)(*[float(v) for v in geom["centre"]])
+        g.pitch = (C.c_double * 3)(*[float(v) for v in geom["pitch"]])
+        g.c = float(geom["c"])
+        self._g = g
+        self.T, self.R, self.F = g.n_tx, g.n_rx, g.n_freq
+        self.M = int(_lib().ora_num_rows(C.byref(g)))
+        self.N = int(_lib().ora_num_voxels(C.byref(g)))
+
+    # --- Sec. II ---------------------------------------------------------------
+    def voxel_position(self, n: int) -> np.ndarray:
+        out = np.zeros(3)
+        _lib().ora_voxel_position(C.byref(self._g), int(n), _ptr(out))
+        return out
+
+    def entry(self, m: int, n: int) -> complex:
+        out = np.zeros(2)
+        _lib().ora_entry(C.byref(self._g), int(m), int(n), _ptr(out))
+        return complex(out[0], out[1])
+
+    def dense(self, rows=None) -> np.ndarray:
+        rows = np.arange(self.M) if rows is None else rows
+        rows = _i32(rows)
+        A = np.zeros((rows.size, self.N), dtype=np.complex128)
+        _lib().ora_dense(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(A))
+        return A
+
+    def forward(self, rows, s) -> np.ndarray:
+        rows, s = _i32(rows), _c128(s).reshape(-1)
+        assert s.size == self.N
+        y = np.zeros(rows.size, dtype=np.complex128)
+        _lib().ora_forward(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(s), _ptr(y))
+        return y
+
+    def forward_sparse(self, rows, idx, vals) -> np.ndarray:
+        rows = _i32(rows)
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+        vals = _c128(vals).reshape(-1)
+        y = np.zeros(rows.size, dtype=np.complex128)
+        _lib().ora_forward_sparse(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(idx, _lp),
+                                  _ptr(vals), idx.size, _ptr(y))
+        return y
+
+    def adjoint(self, rows, r) -> np.ndarray:
+        rows, r = _i32(rows), _c128(r).reshape(-1)
+        assert r.size == rows.size
+        g = np.zeros(self.N, dtype=np.complex128)
+        _lib().ora_adjoint(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(r), _ptr(g))
+        return g
+
+    # --- Sec. IV ---------------------------------------------------------------
+    def gradient(self, rows, y, s) -> np.ndarray:
+        rows, y, s = _i32(rows), _c128(y).reshape(-1), _c128(s).reshape(-1)
+        assert y.size == self.M and s.size == self.N
+        out = np.zeros(self.N, dtype=np.complex128)
+        _lib().ora_stochastic_gradient(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(y), _ptr(s), _ptr(out))
+        return out
+
+    def step(self, rows, y, s, eta: float, alpha: float) -> np.ndarray:
+        rows, y = _i32(rows), _c128(y).reshape(-1)
+        s = _c128(s).reshape(-1).copy()
+        assert y.size == self.M and s.size == self.N
+        _lib().ora_step(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(y), _ptr(s), float(eta), float(alpha))
+        return s
+
+    def solve(self, rows_table, y, s0, eta: float, alpha: float) -> np.ndarray:
+        """K iterations; ``rows_table`` is K x B (iteration k uses row k)."""
+        rows = _i32(rows_table)
+        K, B = rows.shape
+        y = _c128(y).reshape(-1)
+        s = _c128(s0).reshape(-1).copy()
+        _lib().ora_solve(C.byref(self._g), _ptr(rows, _ip), K, B, _ptr(y), _ptr(s), float(eta), float(alpha))
+        return s
+
+    def lambda_max(self, y) -> float:
+        """max_n |(A^H y)_n| / M: for lambda at or above it, s = 0 minimises Eq. 3 with Eq. 4."""
+        g = self.adjoint(np.arange(self.M), y)
+        return float(np.max(np.abs(g)) / self.M)
+
+    def lipschitz(self, rows, iters: int = 100, seed: int = 0) -> float:
+        """Largest eigenvalue of A_B^H A_B / B by power iteration (FP64)."""
+        rng = np.random.default_rng(seed)
+        rows = _i32(rows)
+        v = rng.standard_normal(self.N) + 1j * rng.standard_normal(self.N)
+        v /= np.linalg.norm(v)
+        lam = 0.0
+        for _ in range(iters):
+            w = self.adjoint(rows, self.forward(rows, v)) / rows.size
+            lam = float(np.real(np.vdot(v, w)))
+            v = w / np.linalg.norm(w)
+        return lam
+
+
+def prox_l1(v, alpha: float) -> np.ndarray:
+    """Complex soft threshold S_alpha(v) = v * max(0, 1 - alpha/|v|) (prox of alpha*||.||_1)."""
+    v = _c128(v).reshape(-1).copy()
+    _lib().ora_prox_l1(_ptr(v), v.size, float(alpha))
+    return v
+
+
+def nmse(x, ref) -> float:
+    """|x - ref|^2 / |ref|^2."""
+    x, ref = np.asarray(x), np.asarray(ref)
+    return float(np.sum(np.abs(x - ref) ** 2) / np.sum(np.abs(ref) ** 2))
+
+
+def rel_l2(x, ref) -> float:
+    return float(np.sqrt(nmse(x, ref)))
+
+
+def psnr_magnitude(x, ref) -> float:
+    """PSNR over magnitudes each normalised to peak 1, with ``ref`` as the reference (Sec. V)."""
+    a = np.abs(np.asarray(x)).reshape(-1)
+    b = np.abs(np.asarray(ref)).reshape(-1)
+    a = a / a.max() if a.max() > 0 else a
+    b = b / b.max() if b.max() > 0 else b
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+def library_path() -> str:
+    return os.path.abspath(ensure_oracle())

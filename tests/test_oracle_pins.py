@@ -1,0 +1,314 @@
+"""Pins for the CPU FP64 oracle: checks against facts fixed by the paper's definitions and by
+mathematics, never against the oracle's own formula retyped.
+
+What each test pins (a plausible mistake it would catch):
+
+* closed forms of Eq. 2 at special geometries (co-located antennas on boresight, Pythagorean
+  distances, phases at exact quarter turns): the 4*pi*d_T*d_R denominator, the sign of the
+  exponent, the 2*pi*f/c factor, the pulse factor and the row order m = (f*T + t)*R + r;
+* Tx/Rx reciprocity of Eq. 2 (swapped antenna arrays, transposed row index);
+* the adjoint identity <A s, r> = <s, A^H r> and agreement with a dense matrix product;
+* the complex soft threshold: closed form, optimality condition and brute-force search;
+* Eq. 6 is an unbiased estimate of the gradient of Eq. 4: minibatches that partition the
+  rows add up to the full gradient;
+* lambda >= max|A^H y|/M keeps the iterate at zero; lambda = 0 with full batches converges
+  to the least-squares solution; lambda > 0 converges to a point meeting the Lasso
+  optimality (KKT) conditions;
+* a single point target back-projects to a peak at its own voxel (Cauchy-Schwarz).
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle, prox_l1, rel_l2
+from paper_2509_00774_amd import workloads as W
+
+
+
+
+def single_voxel_geom(tx, rx, freq, z, pulse=None, c=3.0e8):
+    return {"tx": np.asarray(tx, float), "rx": np.asarray(rx, float), "freq": np.asarray(freq, float),
+            "pulse": pulse, "grid": (1, 1, 1), "centre": np.array([0.0, 0.0, z]),
+            "pitch": np.array([1e-3, 1e-3, 1e-3]), "c": c}
+
+
+def small_geom(T=3, R=4, F=5, grid=(4, 3, 2), seed=0, pulse=None):
+    return W.make_geometry(T, R, F, (20e9, 30e9), grid, 5e-3, 0.25, 0.2, pulse=pulse, seed=seed)
+
+
+# ---------------------------------------------------------------------------------------
+# Eq. 2 closed forms
+# ---------------------------------------------------------------------------------------
+def test_boresight_quarter_turns():
+    """Tx = Rx = origin, voxel at (0,0,h): d_T = d_R = h, so A = p exp(-j 2 pi k)/(4 pi h^2)
+    with k = 2 f h / c turns.  k = 40, 40.5, 40.25, 40.75 give the factors 1, -1, -j, +j."""
+    h, c = 0.3, 3.0e8
+    turns = np.array([40.0, 40.5, 40.25, 40.75])
+    freq = turns * c / (2 * h)
+    p = 0.6 + 0.8j
+    orc = Oracle(single_voxel_geom([[0, 0, 0]], [[0, 0, 0]], freq, h, pulse=np.full(4, p)))
+    base = 1.0 / (4 * np.pi * h * h)
+    expect = p * base * np.array([1.0, -1.0, -1j, 1j])
+    got = np.array([orc.entry(m, 0) for m in range(4)])
+    assert np.allclose(got, expect, rtol=0, atol=1e-12 * base)
+    assert abs(base - 0.8841941282883075) < 1e-15  # 1/(4 pi 0.09)
+
+
+def test_pythagorean_distances_and_row_order():
+    """Voxel at (0,0,1.2); Tx at (0.5,0,0), (0,0.9,0) give d_T = 1.3, 1.5 (5-12-13, 3-4-5 triples);
+    Rx at (1.6,0,0), (0,-0.5,0), (-3.5,0,0) give d_R = 2.0, 1.3, 3.7 (3-4-5, 5-12-13, 12-35-37).
+    With f/c = 10 turns/m every round trip is a whole number of turns (real entries); with
+    f/c = 12.5 turns/m the fractional turns are 1/4, 1/2, 1/2, 3/4, 0, 0."""
+    c = 3.0e8
+    tx = [[0.5, 0, 0], [0, 0.9, 0]]
+    rx = [[1.6, 0, 0], [0, -0.5, 0], [-3.5, 0, 0]]
+    freq = [10.0 * c, 12.5 * c]
+    orc = Oracle(single_voxel_geom(tx, rx, freq, 1.2, c=c))
+    dT = [1.3, 1.5]
+    dR = [2.0, 1.3, 3.7]
+    # exp(-j 2 pi frac) for the fractional turn of (f/c)(d_T + d_R)
+    frac_factor = {0.0: 1.0, 0.25: -1j, 0.5: -1.0, 0.75: 1j}
+    frac = {
+        (0, 0, 0): 0.0, (0, 0, 1): 0.0, (0, 0, 2): 0.0, (0, 1, 0): 0.0, (0, 1, 1): 0.0, (0, 1, 2): 0.0,
+        # 12.5 * (3.3, 2.6, 5.0, 3.5, 2.8, 5.2) = 41.25, 32.5, 62.5, 43.75, 35, 65
+        (1, 0, 0): 0.25, (1, 0, 1): 0.5, (1, 0, 2): 0.5, (1, 1, 0): 0.75, (1, 1, 1): 0.0, (1, 1, 2): 0.0,
+    }
+    assert orc.M == 12 and orc.N == 1
+    for (f, t, r), fr in frac.items():
+        m = (f * 2 + t) * 3 + r
+        expect = frac_factor[fr] / (4 * np.pi * dT[t] * dR[r])
+        got = orc.entry(m, 0)
+        assert abs(got - expect) < 1e-12 * abs(expect), (f, t, r, got, expect)
+
+
+def test_voxel_grid_positions():
+    """Voxel centres r = centre + (i - (n-1)/2) * pitch with n = (iz*ny + iy)*nx + ix."""
+    geom = small_geom(grid=(4, 3, 2))
+    orc = Oracle(geom)
+    n = (1 * 3 + 2) * 4 + 3  # ix=3, iy=2, iz=1
+    expect = np.array([0.0, 0.0, 0.25]) + (np.array([3, 2, 1]) - np.array([1.5, 1.0, 0.5])) * 5e-3
+    assert np.allclose(orc.voxel_position(n), expect, atol=1e-15)
+
+
+def test_txrx_reciprocity():
+    """Eq. 2 is symmetric in the two antennas: swapping the Tx and Rx arrays maps
+    row (f, t, r) to row (f, r, t) with the same entry."""
+    geom = small_geom(T=3, R=4, F=3, seed=5, pulse=np.array([1.0, 0.5j, -0.2 + 0.1j]))
+    swapped = dict(geom, tx=geom["rx"], rx=geom["tx"])
+    A = Oracle(geom).dense()
+    As = Oracle(swapped).dense()
+    T, R, F = 3, 4, 3
+    for f in range(F):
+        for t in range(T):
+            for r in range(R):
+                assert np.allclose(As[(f * R + r) * T + t], A[(f * T + t) * R + r], rtol=1e-14, atol=0)
+
+
+def test_amplitude_and_pulse_modulus():
+    """|A_{m,n}| * 4 pi d_T d_R = |p(f_m)| for every entry (distances from numpy)."""
+    pulse = W.gaussian_pulse(np.linspace(20e9, 30e9, 5))
+    geom = small_geom(T=2, R=3, F=5, seed=3, pulse=pulse)
+    orc = Oracle(geom)
+    A = orc.dense()
+    for m in range(orc.M):
+        f, rem = divmod(m, 6)
+        t, r = divmod(rem, 3)
+        for n in range(orc.N):
+            rn = orc.voxel_position(n)
+            dT = np.linalg.norm(geom["tx"][t] - rn)
+            dR = np.linalg.norm(geom["rx"][r] - rn)
+            assert abs(abs(A[m, n]) * 4 * np.pi * dT * dR - abs(pulse[f])) < 1e-13
+
+
+# ---------------------------------------------------------------------------------------
+# Forward / adjoint
+# ---------------------------------------------------------------------------------------
+def test_forward_adjoint_match_dense_product():
+    geom = small_geom(T=3, R=4, F=5, seed=1)
+    orc = Oracle(geom)
+    rows = np.array([7, 0, 59, 33, 12, 12, 41])  # includes a repeated row
+    A = orc.dense(rows)
+    s = W.random_complex(orc.N, seed=2)
+    r = W.random_complex(rows.size, seed=3)
+    assert rel_l2(orc.forward(rows, s), A @ s) < 1e-14
+    assert rel_l2(orc.adjoint(rows, r), A.conj().T @ r) < 1e-14
+
+
+def test_adjoint_identity_c0_sized():
+    geom = W.config_geometry("c0")
+    orc = Oracle(geom)
+    rows = W.draw_rows(orc.M, 64, 1, seed=11)[0]
+    s = W.random_complex(orc.N, seed=12)
+    r = W.random_complex(rows.size, seed=13)
+    lhs = np.vdot(r, orc.forward(rows, s))      # <A s, r> = r^H A s
+    rhs = np.vdot(orc.adjoint(rows, r), s)      # <s, A^H r> = (A^H r)^H s
+    scale = np.linalg.norm(orc.forward(rows, s)) * np.linalg.norm(r)
+    assert abs(lhs - rhs) / scale < 1e-13
+
+
+def test_linearity():
+    geom = small_geom(seed=4)
+    orc = Oracle(geom)
+    rows = np.arange(orc.M)
+    a, b = 0.3 - 1.1j, -2.0 + 0.5j
+    s1, s2 = W.random_complex(orc.N, 5), W.random_complex(orc.N, 6)
+    lhs = orc.forward(rows, a * s1 + b * s2)
+    rhs = a * orc.forward(rows, s1) + b * orc.forward(rows, s2)
+    assert rel_l2(lhs, rhs) < 1e-14
+
+
+def test_forward_sparse_equals_forward():
+    geom = small_geom(seed=8)
+    orc = Oracle(geom)
+    s, idx = W.random_scene(orc.N, 0.2, seed=9)
+    rows = np.arange(orc.M)
+    assert rel_l2(orc.forward_sparse(rows, idx, s[idx]), orc.forward(rows, s)) < 1e-14
+
+
+# ---------------------------------------------------------------------------------------
+# Complex soft threshold (prox of alpha * sum |s_n|)
+# ---------------------------------------------------------------------------------------
+def test_prox_closed_form_and_ties():
+    v = np.array([0.0, 0.5, 3 + 4j, -0.6j, 1e-3 + 0j, 2.0])
+    a = 0.5
+    out = prox_l1(v, a)
+    assert out[0] == 0 and out[1] == 0          # |v| <= a -> 0 (tie included)
+    assert np.allclose(out[2], (3 + 4j) * (1 - 0.5 / 5))  # modulus shrinks by a, phase kept
+    assert np.allclose(out[3], -0.1j)
+    assert out[4] == 0
+    assert np.allclose(out[5], 1.5)
+
+
+def test_prox_optimality_and_bruteforce():
+    """u = S_a(v) minimises 1/2|u - v|^2 + a|u|: v - u = a u/|u| if u != 0, else |v| <= a;
+    and no point of a fine 2-D grid around u does better."""
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    a = 0.7
+    u = prox_l1(v, a)
+    for vi, ui in zip(v, u):
+        if ui != 0:
+            assert abs((vi - ui) - a * ui / abs(ui)) < 1e-12
+        else:
+            assert abs(vi) <= a
+        obj = lambda z: 0.5 * np.abs(z - vi) ** 2 + a * np.abs(z)
+        grid = ui + (np.linspace(-0.05, 0.05, 41)[:, None] + 1j * np.linspace(-0.05, 0.05, 41)[None, :])
+        assert obj(ui) <= obj(grid).min() + 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# Eq. 4 / Eq. 6 gradient
+# ---------------------------------------------------------------------------------------
+def test_minibatch_partition_is_unbiased():
+    """sum over a partition of the rows of (B/M) * grad_B = grad D (Eq. 4 as a mean of Eq. 6)."""
+    geom = small_geom(T=4, R=4, F=4, grid=(3, 3, 2), seed=21)
+    orc = Oracle(geom)
+    M = orc.M  # 64
+    y = W.random_complex(M, seed=22)
+    s = W.random_complex(orc.N, seed=23)
+    perm = np.random.default_rng(24).permutation(M)
+    B = 16
+    total = sum((B / M) * orc.gradient(perm[i:i + B], y, s) for i in range(0, M, B))
+    full = orc.gradient(np.arange(M), y, s)
+    assert rel_l2(total, full) < 1e-13
+    # and the full gradient is (1/M) A^H (A s - y), with A from the dense matrix product
+    A = orc.dense()
+    assert rel_l2(full, A.conj().T @ (A @ s - y) / M) < 1e-13
+
+
+def test_step_is_descent_on_the_objective():
+    """With eta below 1/L, one PGM step cannot increase D(s) + lambda |s|_1."""
+    geom = small_geom(T=3, R=3, F=4, grid=(2, 2, 2), seed=31)
+    orc = Oracle(geom)
+    A = orc.dense()
+    y = W.random_complex(orc.M, seed=32)
+    L = np.linalg.eigvalsh(A.conj().T @ A / orc.M).max()
+    eta, lam = 0.9 / L, 0.2 * orc.lambda_max(y)
+    obj = lambda s: np.sum(np.abs(y - A @ s) ** 2) / (2 * orc.M) + lam * np.sum(np.abs(s))
+    s = W.random_complex(orc.N, seed=33)
+    for _ in range(5):
+        s_new = orc.step(np.arange(orc.M), y, s, eta, lam * eta)
+        assert obj(s_new) <= obj(s) + 1e-15
+        s = s_new
+
+
+# ---------------------------------------------------------------------------------------
+# Solver special cases
+# ---------------------------------------------------------------------------------------
+def test_lambda_max_keeps_zero():
+    geom = small_geom(T=3, R=4, F=4, grid=(3, 2, 2), seed=41)
+    orc = Oracle(geom)
+    s_true, idx = W.random_scene(orc.N, 0.25, seed=42)
+    y = orc.forward(np.arange(orc.M), s_true)
+    lam_max = orc.lambda_max(y)
+    rows = np.tile(np.arange(orc.M), (20, 1))
+    eta = 1.0 / orc.lipschitz(np.arange(orc.M), iters=50)
+    s = orc.solve(rows, y, np.zeros(orc.N), eta, 1.0001 * lam_max * eta)
+    assert np.all(s == 0)
+    # just below lambda_max the first step leaves exactly the arg-max voxel(s) non-zero
+    s1 = orc.step(np.arange(orc.M), y, np.zeros(orc.N), eta, 0.999 * lam_max * eta)
+    g = np.abs(orc.adjoint(np.arange(orc.M), y))
+    assert np.count_nonzero(s1) >= 1 and np.argmax(np.abs(s1)) == np.argmax(g)
+
+
+def test_lambda_zero_full_batch_converges_to_least_squares():
+    """M = 36 > N = 8: with lambda = 0 and B = M, PGM is gradient descent on Eq. 4 and
+    converges to the least-squares solution given by numpy.linalg.lstsq."""
+    geom = small_geom(T=3, R=3, F=4, grid=(2, 2, 2), seed=51)
+    orc = Oracle(geom)
+    A = orc.dense()
+    y = W.random_complex(orc.M, seed=52)
+    L = np.linalg.eigvalsh(A.conj().T @ A / orc.M).max()
+    lmin = np.linalg.eigvalsh(A.conj().T @ A / orc.M).min()
+    K = int(np.ceil(40 * L / lmin))
+    s = orc.solve(np.tile(np.arange(orc.M), (K, 1)), y, np.zeros(orc.N), 1.0 / L, 0.0)
+    ls = np.linalg.lstsq(A, y, rcond=None)[0]
+    assert rel_l2(s, ls) < 1e-8
+
+
+def test_lasso_kkt_at_convergence():
+    """At the limit of PGM with lambda > 0: (1/M) A^H (y - A s) equals lambda s_n/|s_n| on the
+    support and has modulus <= lambda off it (optimality of Eq. 3 with R = |.|_1)."""
+    geom = small_geom(T=3, R=3, F=4, grid=(3, 2, 2), seed=61)
+    orc = Oracle(geom)
+    A = orc.dense()
+    s_true, _ = W.random_scene(orc.N, 0.25, seed=62)
+    y = A @ s_true + 0.01 * W.random_complex(orc.M, seed=63)
+    lam = 0.2 * orc.lambda_max(y)
+    L = np.linalg.eigvalsh(A.conj().T @ A / orc.M).max()
+    s = orc.solve(np.tile(np.arange(orc.M), (6000, 1)), y, np.zeros(orc.N), 1.0 / L, lam / L)
+    corr = A.conj().T @ (y - A @ s) / orc.M
+    on = s != 0
+    assert on.any() and (~on).any()
+    assert np.allclose(corr[on], lam * s[on] / np.abs(s[on]), atol=1e-9 * lam)
+    assert np.all(np.abs(corr[~on]) <= lam * (1 + 1e-9))
+
+
+def test_point_target_backprojection_peak():
+    """s = e_{n0}: |(A^H A e_{n0})_n| / |a_n| is maximal at n = n0, since
+    |a_n^H a_{n0}| <= |a_n| |a_{n0}| with equality only for parallel columns."""
+    geom = W.make_geometry(8, 8, 16, (20e9, 30e9), (8, 8, 4), 5e-3, 0.25, 0.2, seed=71)
+    orc = Oracle(geom)
+    rows = np.arange(orc.M)
+    A = orc.dense(rows)
+    colnorm = np.linalg.norm(A, axis=0)
+    for n0 in np.random.default_rng(72).choice(orc.N, size=12, replace=False):
+        e = np.zeros(orc.N, complex)
+        e[n0] = 1
+        h = orc.adjoint(rows, orc.forward(rows, e))
+        assert np.argmax(np.abs(h) / colnorm) == n0
+        assert np.argmax(np.abs(h)) == n0  # the raw response also peaks there for this array
+
+
+def test_solve_equals_repeated_steps_and_resumes():
+    geom = small_geom(seed=81)
+    orc = Oracle(geom)
+    y = W.random_complex(orc.M, seed=82)
+    rows = W.draw_rows(orc.M, 10, 6, seed=83)
+    s0 = W.random_complex(orc.N, seed=84)
+    s = s0.copy()
+    for k in range(6):
+        s = orc.step(rows[k], y, s, 0.01, 0.001)
+    full = orc.solve(rows, y, s0, 0.01, 0.001)
+    assert np.array_equal(full, s)
+    half = orc.solve(rows[:3], y, s0, 0.01, 0.001)
+    assert np.array_equal(orc.solve(rows[3:], y, half, 0.01, 0.001), full)
