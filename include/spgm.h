@@ -1,0 +1,124 @@
+/*
+ * spgm.h -- C ABI of libspgm.so, the MI355X (gfx950) matrix-free stochastic projector for
+ * l1-regularised near-field MIMO imaging with the stochastic proximal gradient method
+ * (O. Oral, arXiv 2509.00774).
+ *
+ * Model (Sec. II, Eqs. 1-2): measurements y in C^M, reflectivity s in C^N, y = A s + w with
+ *     A_{m,n} = p(f_m) exp(-j 2 pi f_m (|r_Tm - r_n| + |r_Rm - r_n|) / c) / (4 pi |r_Tm - r_n| |r_Rm - r_n|).
+ * The library never stores A: every call forms the entries it needs on the GPU.
+ *
+ * Conventions shared by every entry point
+ *   - complex numbers are complex64: interleaved (re, im) float32, the layout of torch.complex64;
+ *   - measurement index m = (i_f * T + i_t) * R + i_r, 0 <= m < M = F*T*R;
+ *   - voxel index n = (i_z * ny + i_y) * nx + i_x, 0 <= n < N = nx*ny*nz, voxel centre
+ *     r_n = centre + (i - (n_axis - 1)/2) * pitch on each axis;
+ *   - a minibatch is `rows`: B measurement indices (int32, device memory).  Rows may repeat;
+ *     a repeated row counts once per occurrence, as in the sum of Eq. 6;
+ *   - pointers named *_d are device pointers owned by the caller and must stay valid until
+ *     the work queued on `stream` has finished; `stream` is a hipStream_t (NULL = the null
+ *     stream).  Calls are asynchronous with respect to the host unless stated otherwise;
+ *   - every call returns an spgm_status code and never throws; spgm_last_error() gives a
+ *     message for the most recent failure on the calling thread;
+ *   - a plan belongs to the device that was current when it was created; calls switch to that
+ *     device for their duration;
+ *   - calls on one plan are not thread-safe and must not overlap on different streams (the
+ *     plan's workspace is shared); distinct plans are independent.
+ */
+#ifndef SPGM_H
+#define SPGM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spgm_status {
+    SPGM_OK = 0,
+    SPGM_E_INVALID = 1,      /* bad argument: null pointer, size out of range, bad geometry */
+    SPGM_E_NOMEM = 2,        /* device allocation failed */
+    SPGM_E_DEVICE = 3,       /* HIP runtime error (no device, launch failure, ...) */
+    SPGM_E_NONFINITE = 4,    /* reserved: non-finite input detected */
+    SPGM_E_UNSUPPORTED = 5,  /* valid request outside what the kernels support */
+    SPGM_E_BADROW = 6        /* a row index outside [0, M) was seen on the device (sticky) */
+} spgm_status;
+
+/* How the phase f_m (d_T + d_R)/c, hundreds of turns, is brought to float32 before sin/cos. */
+typedef enum spgm_phase_mode {
+    /* Default.  Per voxel tile, the reference round trip of every row is formed and reduced
+     * modulo one turn in float64; each voxel adds its small offset from the tile centre,
+     * computed in float32 from the exact difference of squared distances. */
+    SPGM_PHASE_COMP32 = 0,
+    /* Distances and phase in float64, reduced modulo one turn in float64, then float32 sin/cos. */
+    SPGM_PHASE_F64 = 1,
+    /* Uncompensated float32 distances and phase (reference for the precision study). */
+    SPGM_PHASE_NAIVE32 = 2
+} spgm_phase_mode;
+
+/* Imaging geometry (Sec. II).  Host pointers; the plan copies what it needs, so the caller may
+ * free them after spgm_plan_create returns. */
+typedef struct spgm_geometry {
+    int32_t n_tx, n_rx, n_freq;   /* T, R, F (each >= 1) */
+    int32_t nx, ny, nz;           /* voxel grid (each >= 1) */
+    const double *tx_xyz;         /* T x 3 transmitter positions r_T (m) */
+    const double *rx_xyz;         /* R x 3 receiver positions r_R (m) */
+    const double *freq_hz;        /* F frequencies f (Hz), > 0 */
+    const double *pulse;          /* F x 2 (re, im) pulse spectrum p(f); NULL means p = 1 */
+    double centre[3];             /* grid centre (m) */
+    double pitch[3];              /* voxel pitch (m), each > 0 */
+    double c;                     /* propagation speed (m/s), > 0 */
+} spgm_geometry;
+
+typedef struct spgm_plan spgm_plan;
+
+/* Create a plan for `geom` on the current HIP device (Sec. II, Eq. 2 defines what it encodes).
+ * Rejects (SPGM_E_INVALID): null pointers, any count < 1, M or N above 2^31 - 1, pitch or c or a
+ * frequency <= 0, a non-finite value, or a voxel closer than 1e-9 m to an antenna (Eq. 2 is
+ * singular there).  SPGM_E_UNSUPPORTED: min(T, R) > 64 or max(T, R) > 4096.  On success
+ * *out owns device memory released by spgm_plan_destroy.  Synchronous. */
+int spgm_plan_create(spgm_plan **out, const spgm_geometry *geom, int32_t phase_mode);
+
+/* Release a plan and its device memory (NULL is a no-op).  Synchronises the plan's device. */
+int spgm_plan_destroy(spgm_plan *plan);
+
+/* M = F*T*R and N = nx*ny*nz of the plan (either output pointer may be NULL). */
+int spgm_plan_dims(const spgm_plan *plan, int64_t *M, int64_t *N);
+
+/* Forward projection of the minibatch (Sec. II, Eq. 1 restricted to rows, Sec. IV-A):
+ *     y_d[j] = sum_n A_{rows_d[j], n} s_d[n],  j < B.
+ * rows_d: int32[B]; s_d: complex64[N]; y_d: complex64[B] (output, may not alias s_d).
+ * 1 <= B <= 2^24.  May grow the plan's workspace (hipMalloc, synchronous) on first use of a
+ * larger B. */
+int spgm_forward(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *s_d, void *y_d,
+                 void *stream);
+
+/* Adjoint (conjugate-transpose) projection of the minibatch, unscaled:
+ *     g_d[n] = sum_j conj(A_{rows_d[j], n}) r_d[j],  n < N.
+ * r_d: complex64[B]; g_d: complex64[N] (output).  Same limits as spgm_forward. */
+int spgm_adjoint(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *r_d, void *g_d,
+                 void *stream);
+
+/* One SPGM iteration (Sec. IV, Eq. 5 with the minibatch gradient of Eq. 6), in place:
+ *     s <- S_alpha( s - (eta/B) A_B^H (A_B s - y_B) ),  S_a(v) = v max(0, 1 - a/|v|),
+ * where y_B gathers y_d at rows_d and alpha = lambda * eta.  y_d: complex64[M] (full
+ * measurement vector); s_d: complex64[N] in/out.  eta > 0, alpha >= 0, finite. */
+int spgm_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d, void *s_d,
+              float eta, float alpha, void *stream);
+
+/* `iters` SPGM iterations; iteration k uses rows_d[k*B .. k*B + B - 1] (rows_d: int32[iters*B]).
+ * Equivalent to `iters` calls of spgm_step.  iters >= 0. */
+int spgm_solve(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, const void *y_d,
+               void *s_d, float eta, float alpha, void *stream);
+
+/* Device-detected errors of earlier calls (currently SPGM_E_BADROW).  Synchronises the plan's
+ * device, writes the sticky status to *status (SPGM_OK if none) and clears it. */
+int spgm_plan_status(spgm_plan *plan, int32_t *status);
+
+/* Message describing the last failure of a call on this thread ("" if none). */
+const char *spgm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGM_H */

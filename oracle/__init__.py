@@ -9,7 +9,7 @@ Functions and the passage each one follows:
 
 * :meth:`Oracle.entry`, :meth:`Oracle.dense`            -- observation-matrix entry (Sec. II, Eq. 2)
 * :meth:`Oracle.forward`, :meth:`Oracle.forward_sparse`  -- y_B = A_B s (Sec. II, Eq. 1)
-* :meth:`Oracle.adjoint`                                 -- A_B^H r (conjugate transpose of Eq. 1)
+* :meth:`Oracle.adjoint`, :meth:`Oracle.adjoint_voxels`  -- A_B^H r (conjugate transpose of Eq. 1)
 * :func:`prox_l1`                                        -- prox of alpha*||.||_1 used in Eq. 5
 * :meth:`Oracle.gradient`                                -- minibatch gradient (Sec. IV-A, Eq. 6)
 * :meth:`Oracle.step`, :meth:`Oracle.solve`              -- SPGM / PGM iteration (Sec. IV, Eq. 5)
@@ -58,6 +58,7 @@ def _lib():
             "ora_forward": (None, [g, _ip, C.c_int32, _dp, _dp]),
             "ora_forward_sparse": (None, [g, _ip, C.c_int32, _lp, _dp, C.c_int64, _dp]),
             "ora_adjoint": (None, [g, _ip, C.c_int32, _dp, _dp]),
+            "ora_adjoint_voxels": (None, [g, _ip, C.c_int32, _dp, _lp, C.c_int64, _dp]),
             "ora_prox_l1": (None, [_dp, C.c_int64, C.c_double]),
             "ora_stochastic_gradient": (None, [g, _ip, C.c_int32, _dp, _dp, _dp]),
             "ora_step": (None, [g, _ip, C.c_int32, _dp, _dp, C.c_double, C.c_double]),
@@ -163,6 +164,15 @@ class Oracle:
         g = np.zeros(self.N, dtype=np.complex128)
         _lib().ora_adjoint(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(r), _ptr(g))
         return g
+
+    def adjoint_voxels(self, rows, r, idx) -> np.ndarray:
+        """(A_B^H r) at the listed voxel indices only."""
+        rows, r = _i32(rows), _c128(r).reshape(-1)
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+        out = np.zeros(idx.size, dtype=np.complex128)
+        _lib().ora_adjoint_voxels(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(r), _ptr(idx, _lp),
+                                  idx.size, _ptr(out))
+        return out
 
     # --- Sec. IV ---------------------------------------------------------------
     def gradient(self, rows, y, s) -> np.ndarray:

@@ -170,6 +170,22 @@ void ora_adjoint(const ora_geometry *g, const int32_t *rows, int32_t B, const do
     }
 }
 
+/* The same sum for a listed subset of voxels: out_k = sum_j conj(A_{rows[j], idx[k]}) r_j. */
+void ora_adjoint_voxels(const ora_geometry *g, const int32_t *rows, int32_t B, const double *r,
+                        const int64_t *idx, int64_t nidx, double *out) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nidx; ++k) {
+        double acc_re = 0.0, acc_im = 0.0, a[2];
+        for (int32_t j = 0; j < B; ++j) {
+            ora_entry(g, rows[j], idx[k], a);
+            acc_re += a[0] * r[2 * j] + a[1] * r[2 * j + 1];
+            acc_im += a[0] * r[2 * j + 1] - a[1] * r[2 * j];
+        }
+        out[2 * k] = acc_re;
+        out[2 * k + 1] = acc_im;
+    }
+}
+
 /* Proximal operator of a * sum_n |s_n| (complex soft threshold), in place. */
 void ora_prox_l1(double *v, int64_t N, double a) {
     for (int64_t n = 0; n < N; ++n) {

@@ -1,0 +1,216 @@
+"""ctypes binding of ``libspgm.so`` (C ABI in ``include/spgm.h``), same names as the C calls.
+
+Argument marshalling only: every step of the projector runs in the library's HIP kernels.
+PyTorch supplies device memory (``torch.complex64`` / ``torch.int32`` CUDA tensors) and the
+current HIP stream.  There is no fallback: if the library is not built, or the call fails,
+an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspgm.so")
+
+SPGM_OK = 0
+SPGM_E_INVALID = 1
+SPGM_E_NOMEM = 2
+SPGM_E_DEVICE = 3
+SPGM_E_NONFINITE = 4
+SPGM_E_UNSUPPORTED = 5
+SPGM_E_BADROW = 6
+
+PHASE_COMP32 = 0
+PHASE_F64 = 1
+PHASE_NAIVE32 = 2
+
+EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
+            "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error")
+
+_dp = C.POINTER(C.c_double)
+
+
+class SpgmGeometry(C.Structure):
+    """Mirror of ``spgm_geometry``."""
+    _fields_ = [
+        ("n_tx", C.c_int32), ("n_rx", C.c_int32), ("n_freq", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("tx_xyz", _dp), ("rx_xyz", _dp), ("freq_hz", _dp), ("pulse", _dp),
+        ("centre", C.c_double * 3), ("pitch", C.c_double * 3), ("c", C.c_double),
+    ]
+
+
+class SpgmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("spgm error %d: %s" % (code, msg))
+        self.code = code
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspgm.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError("libspgm.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = C.CDLL(path)
+    vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
+    sigs = {
+        "spgm_plan_create": [C.POINTER(vp), C.POINTER(SpgmGeometry), i32],
+        "spgm_plan_destroy": [vp],
+        "spgm_plan_dims": [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+        "spgm_forward": [vp, vp, i32, vp, vp, vp],
+        "spgm_adjoint": [vp, vp, i32, vp, vp, vp],
+        "spgm_step": [vp, vp, i32, vp, vp, f32, f32, vp],
+        "spgm_solve": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
+        "spgm_plan_status": [vp, C.POINTER(i32)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.spgm_last_error.argtypes = []
+    lib.spgm_last_error.restype = C.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(rc):
+    if rc != SPGM_OK:
+        msg = load_library().spgm_last_error().decode(errors="replace")
+        raise SpgmError(rc, msg)
+
+
+def make_geometry_struct(geom):
+    """Build an ``SpgmGeometry`` from the geometry dict of :mod:`.workloads`.
+    Returns (struct, keep-alive list)."""
+    tx = np.ascontiguousarray(np.asarray(geom["tx"], dtype=np.float64).reshape(-1, 3))
+    rx = np.ascontiguousarray(np.asarray(geom["rx"], dtype=np.float64).reshape(-1, 3))
+    fr = np.ascontiguousarray(np.asarray(geom["freq"], dtype=np.float64).reshape(-1))
+    pulse = geom.get("pulse")
+    pl = None
+    if pulse is not None:
+        pulse = np.asarray(pulse, dtype=np.complex128).reshape(-1)
+        pl = np.ascontiguousarray(np.stack([pulse.real, pulse.imag], -1).reshape(-1))
+    g = SpgmGeometry()
+    g.n_tx, g.n_rx, g.n_freq = tx.shape[0], rx.shape[0], fr.shape[0]
+    g.nx, g.ny, g.nz = (int(v) for v in geom["grid"])
+    g.tx_xyz = tx.ctypes.data_as(_dp)
+    g.rx_xyz = rx.ctypes.data_as(_dp)
+    g.freq_hz = fr.ctypes.data_as(_dp)
+    g.pulse = pl.ctypes.data_as(_dp) if pl is not None else _dp()
+    g.centre = (C.c_double * 3)(*[float(v) for v in geom["centre"]])
+    g.pitch = (C.c_double * 3)(*[float(v) for v in np.broadcast_to(geom["pitch"], (3,))])
+    g.c = float(geom["c"])
+    return g, [tx, rx, fr, pl]
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan (``spgm_plan``) for one geometry on the current device."""
+
+    def __init__(self, geom, phase_mode: int = PHASE_COMP32):
+        lib = load_library()
+        g, keep = make_geometry_struct(geom)
+        h = C.c_void_p()
+        _check(lib.spgm_plan_create(C.byref(h), C.byref(g), int(phase_mode)))
+        del keep
+        self._h = h
+        self._lib = lib
+        M, N = C.c_int64(), C.c_int64()
+        _check(lib.spgm_plan_dims(h, C.byref(M), C.byref(N)))
+        self.M, self.N = M.value, N.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.spgm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # --- calls ---------------------------------------------------------------------------
+    def spgm_forward(self, rows, s, out=None, stream=None):
+        import torch
+        B = rows.numel()
+        if out is None:
+            out = torch.empty(B, dtype=torch.complex64, device=s.device)
+        _check(self._lib.spgm_forward(self._h, _dev(rows, torch.int32, "rows"), B,
+                                      _dev(s, torch.complex64, "s", self.N),
+                                      _dev(out, torch.complex64, "out", B), _stream_ptr(stream)))
+        return out
+
+    def spgm_adjoint(self, rows, r, out=None, stream=None):
+        import torch
+        B = rows.numel()
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.complex64, device=r.device)
+        _check(self._lib.spgm_adjoint(self._h, _dev(rows, torch.int32, "rows"), B,
+                                      _dev(r, torch.complex64, "r", B),
+                                      _dev(out, torch.complex64, "out", self.N), _stream_ptr(stream)))
+        return out
+
+    def spgm_step(self, rows, y, s, eta, alpha, stream=None):
+        import torch
+        B = rows.numel()
+        _check(self._lib.spgm_step(self._h, _dev(rows, torch.int32, "rows"), B,
+                                   _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
+                                   float(eta), float(alpha), _stream_ptr(stream)))
+        return s
+
+    def spgm_solve(self, rows_table, y, s, eta, alpha, stream=None):
+        """``rows_table``: int32 tensor of shape (iters, B)."""
+        import torch
+        if rows_table.dim() != 2:
+            raise ValueError("rows_table must be 2-D (iters, B)")
+        K, B = rows_table.shape
+        _check(self._lib.spgm_solve(self._h, _dev(rows_table, torch.int32, "rows_table"), int(K), int(B),
+                                    _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
+                                    float(eta), float(alpha), _stream_ptr(stream)))
+        return s
+
+    def spgm_plan_status(self):
+        st = C.c_int32()
+        _check(self._lib.spgm_plan_status(self._h, C.byref(st)))
+        return st.value
+
+    # short aliases
+    forward = spgm_forward
+    adjoint = spgm_adjoint
+    step = spgm_step
+    solve = spgm_solve
+    status = spgm_plan_status

@@ -1,0 +1,900 @@
+// spgm.hip -- gfx950 kernels and C-ABI of the matrix-free SPGM near-field MIMO projector.
+//
+// The observation matrix of Sec. II, Eq. 2,
+//     A_{m,n} = p(f_m) exp(-j 2 pi f_m (d_T + d_R) / c) / (4 pi d_T d_R),
+// is never stored: every launch forms the entries of its (row chunk x voxel tile) block in
+// registers and applies them at once.  One SPGM iteration (Sec. IV, Eq. 5 with the gradient of
+// Eq. 6) is five launches on the caller's stream:
+//   1. k_sort_rows   sort the minibatch by (G antenna, L antenna, frequency) so that rows that
+//                    share an antenna pair are adjacent and share their per-voxel geometry;
+//   2. k_fwd_tile    per (voxel brick, row range): partial row sums of A_B s over the brick;
+//   3. k_row_reduce  per row: sum of the brick partials in a fixed order, times p(f)/(4 pi),
+//                    minus y_m (the residual of Eq. 6), pre-multiplied by conj(p(f)/(4 pi));
+//   4. k_adj_tile    per (voxel brick, row range): partial column sums of A_B^H r, one voxel
+//                    per lane and no atomics;
+//   5. k_col_reduce  per voxel: sum of the row-range partials in a fixed order, gradient step
+//                    and complex soft threshold (the prox of the l1 norm in Eq. 5).
+// Every reduction runs in a fixed order, so results are bitwise reproducible run to run.
+//
+// Geometry per tile.  The grid is cut into 8 x 8 x 4 voxel bricks (one brick per work-group of
+// 256 lanes; each lane owns one (x, y) column of 4 voxels).  The two antenna arrays are called
+// G (the sort-major side, whose per-voxel distance terms live in registers and are rebuilt when
+// the G antenna changes) and L (the other side, whose per-voxel terms are staged in LDS for
+// every L antenna).  L is the smaller array.
+//
+// Phase (SPGM_PHASE_COMP32).  With c the brick centre, e = r_n - c and g_a = c - r_a,
+//     d_{a,n} - d_{a,c} = (|e|^2 + 2 e.g_a) / (d_{a,n} + d_{a,c})
+// holds exactly and is evaluated in float32 with small relative error because |e| is a few
+// millimetres.  The round-trip phase in turns is split as
+//     f/c (d_T + d_R) = [f/c (d_{T,c} + d_{R,c})  mod 1]  +  f/c (delta_T + delta_R),
+// the first term formed in float64 once per (row, brick), the second in float32 per entry.
+// The result lies within a few turns of zero, where v_sin_f32 / v_cos_f32 (argument in turns)
+// are accurate to about 1.2e-7 absolute, so no further range reduction is applied.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "spgm.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kThreads = 256;                 // 4 waves per work-group
+constexpr int kBX = 8, kBY = 8, kBZ = 4;      // voxel brick
+constexpr int kBrick = kBX * kBY * kBZ;       // 256 voxels, one (x, y) column per lane
+constexpr int kP = kBZ;                       // voxels per lane
+constexpr int kSub = 256;                     // rows staged in LDS at a time (64 per wave)
+constexpr int kMaxL = 64;                     // largest L array (LDS: kMaxL * 256 * 8 B)
+constexpr int kMaxAnt = 512;                  // T + R
+constexpr int kSortChunk = 16384;             // rows sorted by one work-group
+constexpr int kSortThreads = 1024;
+constexpr int kMaxB = 1 << 24;
+
+struct Geo {
+    const double *ant;    // (T + R) x 3 positions, transmitters first
+    const double *kappa;  // F: f / c in turns per metre
+    const float2 *q;      // F: p(f) / (4 pi)
+    int T, R, F;
+    int nx, ny, nz;
+    int nbx, nby, nbz;    // bricks per axis
+    int g_is_tx;          // 1: G = transmitters, L = receivers
+    int nG, nL;
+    double cx, cy, cz;    // grid centre
+    double px, py, pz;    // pitch
+};
+
+// ------------------------------------------------------------------------------------------
+// Device helpers
+// ------------------------------------------------------------------------------------------
+
+// Sum over the 64 lanes of a wave with DPP row operations; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x140, 0xF, 0xF, true);  // row_mirror
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xA, 0xF, false); // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xC, 0xF, false); // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Brick decomposition of a tile index.
+__device__ __forceinline__ void brick_of(const Geo &g, int tile, int &bx, int &by, int &bz) {
+    bx = tile % g.nbx;
+    by = (tile / g.nbx) % g.nby;
+    bz = tile / (g.nbx * g.nby);
+}
+
+// Offset of local voxel (lx, ly, lz) from the brick centre, metres, float32.
+__device__ __forceinline__ void local_offset(const Geo &g, int lx, int ly, int lz, float &ex, float &ey,
+                                             float &ez) {
+    ex = (float)((lx - 0.5 * (kBX - 1)) * g.px);
+    ey = (float)((ly - 0.5 * (kBY - 1)) * g.py);
+    ez = (float)((lz - 0.5 * (kBZ - 1)) * g.pz);
+}
+
+// Distance offset delta = d_{a,n} - d_{a,c} and amplitude w = 1/d_{a,n} for a voxel at offset e
+// from the brick centre; ga = (c - r_a, |c - r_a|) in float32.
+__device__ __forceinline__ void comp_offset(float ex, float ey, float ez, float4 ga, float &delta, float &w) {
+    const float vx = ex + ga.x, vy = ey + ga.y, vz = ez + ga.z;
+    const float d2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
+    const float d = sqrtf(d2);
+    const float ee = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+    const float num = fmaf(2.0f, fmaf(ex, ga.x, fmaf(ey, ga.y, ez * ga.z)), ee);
+    delta = num / (d + ga.w);
+    w = 1.0f / d;
+}
+
+// Decode measurement index m = (f*T + t)*R + r into (f, G index, L index).
+__device__ __forceinline__ void decode_row(const Geo &g, int m, int &f, int &gi, int &li) {
+    const int r = m % g.R;
+    const int t = (m / g.R) % g.T;
+    f = m / (g.R * g.T);
+    gi = g.g_is_tx ? t : r;
+    li = g.g_is_tx ? r : t;
+}
+
+__device__ __forceinline__ int ant_of_g(const Geo &g, int gi) { return g.g_is_tx ? gi : g.T + gi; }
+__device__ __forceinline__ int ant_of_l(const Geo &g, int li) { return g.g_is_tx ? g.T + li : li; }
+
+// ------------------------------------------------------------------------------------------
+// 1. Sort the minibatch by (G, L, f, original position), one work-group per chunk of rows.
+//    Output srt[i] = (original position j, f, G index, L index) of the i-th sorted row.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void k_sort_rows(Geo g, const int32_t *__restrict__ rows, int B,
+                                                            int4 *__restrict__ srt, int *__restrict__ status) {
+    __shared__ unsigned long long keys[kSortChunk];
+    const int c0 = blockIdx.x * kSortChunk;
+    const int n = min(kSortChunk, B - c0);
+    int p2 = 2;
+    while (p2 < n) p2 <<= 1;
+    const int M = g.F * g.T * g.R;
+    for (int i = threadIdx.x; i < p2; i += kSortThreads) {
+        unsigned long long key = ~0ull;
+        if (i < n) {
+            int m = rows[c0 + i];
+            if (m < 0 || m >= M) {
+                atomicOr(status, 1);
+                m = 0;
+            }
+            int f, gi, li;
+            decode_row(g, m, f, gi, li);
+            const unsigned int pk = (unsigned int)((gi * g.nL + li) * g.F + f);
+            key = ((unsigned long long)pk << 32) | (unsigned int)i;
+        }
+        keys[i] = key;
+    }
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < p2; i += kSortThreads) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long a = keys[i], b = keys[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        keys[i] = b;
+                        keys[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += kSortThreads) {
+        const unsigned long long key = keys[i];
+        const int j = (int)(key & 0xffffffffu);
+        const unsigned int pk = (unsigned int)(key >> 32);
+        const int f = (int)(pk % (unsigned int)g.F);
+        const unsigned int pair = pk / (unsigned int)g.F;
+        const int li = (int)(pair % (unsigned int)g.nL);
+        const int gi = (int)(pair / (unsigned int)g.nL);
+        srt[c0 + i] = make_int4(c0 + j, f, gi, li);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Shared prologue of the two tile kernels: antenna terms relative to the brick centre and the
+// L-side per-voxel terms, staged in LDS.
+// ------------------------------------------------------------------------------------------
+struct TileSmem {
+    float4 *antg;   // [T+R]: (c - r_a) float32, |c - r_a| float32
+    double *antd;   // [T+R]: |c - r_a| float64
+    float2 *lside;  // [nL][256]: (delta, w) per L antenna per brick voxel
+    float *kap;     // [kSub]
+    float *ref;     // [kSub]
+    int *gl;        // [kSub]: G index | L index << 16
+    float2 *rowv;   // [kSub]: forward row sums / adjoint scaled residuals
+};
+
+__device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
+    TileSmem t;
+    const int A = g.T + g.R;
+    t.antg = reinterpret_cast<float4 *>(smem);
+    t.antd = reinterpret_cast<double *>(smem + sizeof(float4) * A);
+    char *p = smem + (sizeof(double) + sizeof(float4)) * A;
+    t.kap = reinterpret_cast<float *>(p);
+    t.ref = t.kap + kSub;
+    t.gl = reinterpret_cast<int *>(t.ref + kSub);
+    t.rowv = reinterpret_cast<float2 *>(t.gl + kSub);
+    t.lside = t.rowv + kSub;
+    return t;
+}
+
+__device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int bx, int by, int bz) {
+    const double ccx = g.cx + (bx * kBX + 0.5 * (kBX - 1) - 0.5 * (g.nx - 1)) * g.px;
+    const double ccy = g.cy + (by * kBY + 0.5 * (kBY - 1) - 0.5 * (g.ny - 1)) * g.py;
+    const double ccz = g.cz + (bz * kBZ + 0.5 * (kBZ - 1) - 0.5 * (g.nz - 1)) * g.pz;
+    const int A = g.T + g.R;
+    for (int a = threadIdx.x; a < A; a += kThreads) {
+        const double gx = ccx - g.ant[3 * a], gy = ccy - g.ant[3 * a + 1], gz = ccz - g.ant[3 * a + 2];
+        const double d = sqrt(gx * gx + gy * gy + gz * gz);
+        sm.antd[a] = d;
+        sm.antg[a] = make_float4((float)gx, (float)gy, (float)gz, (float)d);
+    }
+    __syncthreads();
+    const int v = threadIdx.x;  // brick voxel: lane -> (x, y), wave -> z
+    float ex, ey, ez;
+    local_offset(g, (v & 63) & 7, (v & 63) >> 3, v >> 6, ex, ey, ez);
+    for (int li = 0; li < g.nL; ++li) {
+        float dl, wl;
+        comp_offset(ex, ey, ez, sm.antg[ant_of_l(g, li)], dl, wl);
+        sm.lside[li * kBrick + v] = make_float2(dl, wl);
+    }
+}
+
+// Stage row data of sorted rows [base, base + nsub): float32 kappa, per-brick reference phase
+// (float64, reduced to [-1/2, 1/2] turn), packed (G, L) indices.
+__device__ __forceinline__ void stage_rows(const Geo &g, const TileSmem &sm, const int4 *__restrict__ srt,
+                                           int base, int nsub) {
+    const int k = threadIdx.x;
+    if (k < nsub) {
+        const int4 info = srt[base + k];
+        const double kap = g.kappa[info.y];
+        double ph = kap * (sm.antd[ant_of_g(g, info.z)] + sm.antd[ant_of_l(g, info.w)]);
+        ph -= rint(ph);
+        sm.kap[k] = (float)kap;
+        sm.ref[k] = (float)ph;
+        sm.gl[k] = info.z | (info.w << 16);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// 2. Forward partials: part[tile][i] = sum over brick voxels of (A_{row i, n} / q_f) s_n.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
+                                                       const float2 *__restrict__ s, float2 *__restrict__ part) {
+    extern __shared__ __align__(16) char smem[];
+    const TileSmem sm = carve(smem, g);
+    const int tile = blockIdx.x;
+    const int r0 = blockIdx.y * rows_per_wg;
+    const int r1 = min(B, r0 + rows_per_wg);
+    int bx, by, bz;
+    brick_of(g, tile, bx, by, bz);
+    stage_tile(g, sm, bx, by, bz);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lx = lane & 7, ly = lane >> 3;
+    const int ix = bx * kBX + lx, iy = by * kBY + ly;
+    float ex[kP], ey[kP], ez[kP], sr[kP], si[kP];
+    bool valid[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+        const int iz = bz * kBZ + p;
+        valid[p] = ix < g.nx && iy < g.ny && iz < g.nz;
+        local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
+        float2 sv = make_float2(0.f, 0.f);
+        if (valid[p]) sv = s[((size_t)iz * g.ny + iy) * g.nx + ix];
+        sr[p] = sv.x;
+        si[p] = sv.y;
+    }
+
+    float dG[kP], usr[kP], usi[kP], D[kP], ur[kP], ui[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) dG[p] = usr[p] = usi[p] = D[p] = ur[p] = ui[p] = 0.f;
+    int cur_g = -1, cur_l = -1;
+
+    for (int base = r0; base < r1; base += kSub) {
+        const int nsub = min(kSub, r1 - base);
+        __syncthreads();  // previous sub-chunk fully consumed; L-side staged
+        stage_rows(g, sm, srt, base, nsub);
+        __syncthreads();
+        const int kb = wave * kWave;
+        const int ke = min(nsub, kb + kWave);
+        for (int k = kb; k < ke; ++k) {
+            const int gl = uniform(sm.gl[k]);
+            const int gi = gl & 0xffff, li = gl >> 16;
+            if (gi != cur_g) {
+                const float4 ga = sm.antg[ant_of_g(g, gi)];
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    float wg;
+                    comp_offset(ex[p], ey[p], ez[p], ga, dG[p], wg);
+                    usr[p] = valid[p] ? wg * sr[p] : 0.f;
+                    usi[p] = valid[p] ? wg * si[p] : 0.f;
+                }
+                cur_g = gi;
+                cur_l = -1;
+            }
+            if (li != cur_l) {
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    const float2 lv = sm.lside[li * kBrick + p * kWave + lane];
+                    D[p] = valid[p] ? dG[p] + lv.x : 0.f;
+                    ur[p] = valid[p] ? lv.y * usr[p] : 0.f;
+                    ui[p] = valid[p] ? lv.y * usi[p] : 0.f;
+                }
+                cur_l = li;
+            }
+            const float kap = sm.kap[k], ref = sm.ref[k];
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int p = 0; p < kP; ++p) {
+                const float ph = fmaf(kap, D[p], ref);
+                const float sn = __builtin_amdgcn_sinf(ph);
+                const float cs = __builtin_amdgcn_cosf(ph);
+                // (cs - j sn)(ur + j ui)
+                ar = fmaf(cs, ur[p], ar);
+                ar = fmaf(sn, ui[p], ar);
+                ai = fmaf(cs, ui[p], ai);
+                ai = fmaf(-sn, ur[p], ai);
+            }
+            ar = wave_sum_to_63(ar);
+            ai = wave_sum_to_63(ai);
+            if (lane == 63) sm.rowv[k] = make_float2(ar, ai);
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nsub) part[(size_t)tile * B + base + threadIdx.x] = sm.rowv[threadIdx.x];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// 3. Row reduction: v_i = q_f * sum_tiles part[tile][i]  (minus y_m when y is given).
+//    out_user[j] = v (caller order); out_scaled[i] = conj(q_f) * v (sorted order, adjoint input).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_row_reduce(Geo g, const float2 *__restrict__ part, int n_tiles, int B,
+                                                    const int4 *__restrict__ srt, const int32_t *__restrict__ rows,
+                                                    const float2 *__restrict__ y, float2 *__restrict__ out_user,
+                                                    float2 *__restrict__ out_scaled) {
+    __shared__ float2 red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + tx;
+    float ar = 0.f, ai = 0.f;
+    if (i < B) {
+        for (int t = ty; t < n_tiles; t += 4) {
+            const float2 v = part[(size_t)t * B + i];
+            ar += v.x;
+            ai += v.y;
+        }
+    }
+    red[ty][tx] = make_float2(ar, ai);
+    __syncthreads();
+    if (ty == 0 && i < B) {
+        ar = red[0][tx].x + red[1][tx].x + red[2][tx].x + red[3][tx].x;
+        ai = red[0][tx].y + red[1][tx].y + red[2][tx].y + red[3][tx].y;
+        const int4 info = srt[i];
+        const float2 q = g.q[info.y];
+        float vr = q.x * ar - q.y * ai;
+        float vi = q.x * ai + q.y * ar;
+        if (y) {
+            int m = rows[info.x];
+            const int M = g.F * g.T * g.R;
+            if (m < 0 || m >= M) m = 0;
+            const float2 ym = y[m];
+            vr -= ym.x;
+            vi -= ym.y;
+        }
+        if (out_user) out_user[info.x] = make_float2(vr, vi);
+        if (out_scaled) out_scaled[i] = make_float2(q.x * vr + q.y * vi, q.x * vi - q.y * vr);
+    }
+}
+
+// Adjoint input for a caller-supplied residual: out_scaled[i] = conj(q_f) * r[j_i].
+__global__ __launch_bounds__(256) void k_gather_scale(Geo g, const int4 *__restrict__ srt, int B,
+                                                      const float2 *__restrict__ r, float2 *__restrict__ out_scaled) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < B) {
+        const int4 info = srt[i];
+        const float2 q = g.q[info.y];
+        const float2 v = r[info.x];
+        out_scaled[i] = make_float2(q.x * v.x + q.y * v.y, q.x * v.y - q.y * v.x);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// 4. Adjoint partials: gpart[split][n] = sum over the split's rows of conj(A_{i,n}/q_f) rs_i,
+//    with rs_i = conj(q_f) r_i, one voxel column per lane, rows shared by the four waves.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
+                                                       const float2 *__restrict__ rs, float2 *__restrict__ gpart,
+                                                       int N) {
+    extern __shared__ __align__(16) char smem[];
+    const TileSmem sm = carve(smem, g);
+    const int tile = blockIdx.x;
+    const int r0 = blockIdx.y * rows_per_wg;
+    const int r1 = min(B, r0 + rows_per_wg);
+    int bx, by, bz;
+    brick_of(g, tile, bx, by, bz);
+    stage_tile(g, sm, bx, by, bz);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lx = lane & 7, ly = lane >> 3;
+    float ex[kP], ey[kP], ez[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
+
+    float dG[kP], wG[kP], D[kP], W[kP], hr[kP], hi[kP], gr[kP], gi_[kP];
+#pragma unroll
+    for (int p = 0; p < kP; ++p) dG[p] = wG[p] = D[p] = W[p] = hr[p] = hi[p] = gr[p] = gi_[p] = 0.f;
+    int cur_g = -1, cur_l = -1;
+
+    for (int base = r0; base < r1; base += kSub) {
+        const int nsub = min(kSub, r1 - base);
+        __syncthreads();
+        stage_rows(g, sm, srt, base, nsub);
+        if ((int)threadIdx.x < nsub) sm.rowv[threadIdx.x] = rs[base + threadIdx.x];
+        __syncthreads();
+        const int kb = wave * kWave;
+        const int ke = min(nsub, kb + kWave);
+        for (int k = kb; k < ke; ++k) {
+            const int gl = uniform(sm.gl[k]);
+            const int gi = gl & 0xffff, li = gl >> 16;
+            if (gi != cur_g || li != cur_l) {
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    gr[p] = fmaf(W[p], hr[p], gr[p]);
+                    gi_[p] = fmaf(W[p], hi[p], gi_[p]);
+                    hr[p] = hi[p] = 0.f;
+                }
+                if (gi != cur_g) {
+                    const float4 ga = sm.antg[ant_of_g(g, gi)];
+#pragma unroll
+                    for (int p = 0; p < kP; ++p) comp_offset(ex[p], ey[p], ez[p], ga, dG[p], wG[p]);
+                    cur_g = gi;
+                }
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    const float2 lv = sm.lside[li * kBrick + p * kWave + lane];
+                    D[p] = dG[p] + lv.x;
+                    W[p] = wG[p] * lv.y;
+                }
+                cur_l = li;
+            }
+            const float kap = sm.kap[k], ref = sm.ref[k];
+            const float2 rv = sm.rowv[k];
+#pragma unroll
+            for (int p = 0; p < kP; ++p) {
+                const float ph = fmaf(kap, D[p], ref);
+                const float sn = __builtin_amdgcn_sinf(ph);
+                const float cs = __builtin_amdgcn_cosf(ph);
+                // (cs + j sn)(rv.x + j rv.y)
+                hr[p] = fmaf(cs, rv.x, hr[p]);
+                hr[p] = fmaf(-sn, rv.y, hr[p]);
+                hi[p] = fmaf(cs, rv.y, hi[p]);
+                hi[p] = fmaf(sn, rv.x, hi[p]);
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
+        gr[p] = fmaf(W[p], hr[p], gr[p]);
+        gi_[p] = fmaf(W[p], hi[p], gi_[p]);
+    }
+    // Combine the four waves in a fixed order.
+    __syncthreads();
+    float2 *red = sm.lside;  // 4 x 256 float2, the L-side terms are no longer needed
+#pragma unroll
+    for (int p = 0; p < kP; ++p) red[wave * kBrick + p * kWave + lane] = make_float2(gr[p], gi_[p]);
+    __syncthreads();
+    const int v = threadIdx.x;
+    const int ix = bx * kBX + ((v & 63) & 7), iy = by * kBY + ((v & 63) >> 3), iz = bz * kBZ + (v >> 6);
+    if (ix < g.nx && iy < g.ny && iz < g.nz) {
+        float2 acc = red[v];
+        for (int w = 1; w < 4; ++w) {
+            acc.x += red[w * kBrick + v].x;
+            acc.y += red[w * kBrick + v].y;
+        }
+        gpart[(size_t)blockIdx.y * N + ((size_t)iz * g.ny + iy) * g.nx + ix] = acc;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// 5. Column reduction over row splits; optional gradient step and complex soft threshold.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_col_reduce(const float2 *__restrict__ gpart, int nsplit, int N,
+                                                    float2 *__restrict__ g_out, float2 *__restrict__ s, float step,
+                                                    float alpha) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float gr = 0.f, gi = 0.f;
+    for (int k = 0; k < nsplit; ++k) {
+        const float2 v = gpart[(size_t)k * N + n];
+        gr += v.x;
+        gi += v.y;
+    }
+    if (g_out) g_out[n] = make_float2(gr, gi);
+    if (s) {
+        float2 v = s[n];
+        v.x = fmaf(-step, gr, v.x);
+        v.y = fmaf(-step, gi, v.y);
+        const float mag = sqrtf(fmaf(v.x, v.x, v.y * v.y));
+        if (mag <= alpha) {
+            v.x = 0.f;
+            v.y = 0.f;
+        } else {
+            const float sc = 1.0f - alpha / mag;
+            v.x *= sc;
+            v.y *= sc;
+        }
+        s[n] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host side
+// ------------------------------------------------------------------------------------------
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok() {
+    g_last_error.clear();
+    return SPGM_OK;
+}
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        if (prev_ != dev) hipSetDevice(dev);
+        dev_ = dev;
+    }
+    ~DeviceGuard() {
+        if (prev_ >= 0 && prev_ != dev_) hipSetDevice(prev_);
+    }
+
+  private:
+    int prev_ = -1, dev_ = 0;
+};
+
+}  // namespace
+
+struct spgm_plan {
+    int device = 0;
+    int phase_mode = 0;
+    int64_t M = 0, N = 0;
+    Geo geo{};
+    int n_tiles = 0;
+    double *d_ant = nullptr;
+    double *d_kappa = nullptr;
+    float2 *d_q = nullptr;
+    int *d_status = nullptr;
+    // workspace, sized for ws_B rows
+    int ws_B = 0;
+    int ws_splits = 0;
+    int4 *d_srt = nullptr;
+    float2 *d_part = nullptr;
+    float2 *d_rs = nullptr;
+    float2 *d_gpart = nullptr;
+    size_t lds_bytes = 0;
+};
+
+namespace {
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Row splits for the tile kernels: enough work-groups to cover the chip a few times, at least
+// 64 rows per work-group.
+int row_splits(const spgm_plan *p, int B) {
+    const int want = std::max(1, (4 * 256 + p->n_tiles - 1) / p->n_tiles);
+    const int maxs = std::max(1, (B + 63) / 64);
+    return std::min(want, maxs);
+}
+
+int ensure_workspace(spgm_plan *p, int B) {
+    const int splits = row_splits(p, B);
+    if (B <= p->ws_B && splits <= p->ws_splits) return SPGM_OK;
+    const int nb = std::max(B, p->ws_B);
+    const int ns = std::max(splits, p->ws_splits);
+    hipFree(p->d_srt);
+    hipFree(p->d_part);
+    hipFree(p->d_rs);
+    hipFree(p->d_gpart);
+    p->d_srt = nullptr;
+    p->d_part = nullptr;
+    p->d_rs = nullptr;
+    p->d_gpart = nullptr;
+    p->ws_B = p->ws_splits = 0;
+    if (hipMalloc(&p->d_srt, sizeof(int4) * (size_t)nb) != hipSuccess ||
+        hipMalloc(&p->d_part, sizeof(float2) * (size_t)nb * p->n_tiles) != hipSuccess ||
+        hipMalloc(&p->d_rs, sizeof(float2) * (size_t)nb) != hipSuccess ||
+        hipMalloc(&p->d_gpart, sizeof(float2) * (size_t)ns * p->N) != hipSuccess) {
+        return fail(SPGM_E_NOMEM, "spgm: workspace allocation failed (B=%d)", nb);
+    }
+    p->ws_B = nb;
+    p->ws_splits = ns;
+    return SPGM_OK;
+}
+
+int launch_check(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SPGM_E_DEVICE, "spgm: %s launch failed: %s", what, hipGetErrorString(e));
+    return SPGM_OK;
+}
+
+int check_common(spgm_plan *p, const int32_t *rows, int B) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm: plan is NULL");
+    if (!rows) return fail(SPGM_E_INVALID, "spgm: rows is NULL");
+    if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm: B=%d outside [1, %d]", B, kMaxB);
+    return SPGM_OK;
+}
+
+int run_sort(spgm_plan *p, const int32_t *rows, int B, hipStream_t st) {
+    const int nchunks = (B + kSortChunk - 1) / kSortChunk;
+    k_sort_rows<<<nchunks, kSortThreads, 0, st>>>(p->geo, rows, B, p->d_srt, p->d_status);
+    return launch_check("sort");
+}
+
+int run_forward_partials(spgm_plan *p, const float2 *s, int B, hipStream_t st) {
+    const int splits = row_splits(p, B);
+    const int rpw = (B + splits - 1) / splits;
+    k_fwd_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, p->d_srt, B, rpw, s, p->d_part);
+    return launch_check("forward");
+}
+
+int run_adjoint_partials(spgm_plan *p, int B, hipStream_t st) {
+    const int splits = row_splits(p, B);
+    const int rpw = (B + splits - 1) / splits;
+    k_adj_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, p->d_srt, B, rpw, p->d_rs,
+                                                                        p->d_gpart, (int)p->N);
+    return launch_check("adjoint");
+}
+
+int step_impl(spgm_plan *p, const int32_t *rows, int B, const float2 *y, float2 *s, float eta, float alpha,
+              hipStream_t st) {
+    int rc;
+    if ((rc = run_sort(p, rows, B, st))) return rc;
+    if ((rc = run_forward_partials(p, s, B, st))) return rc;
+    k_row_reduce<<<(B + 63) / 64, 256, 0, st>>>(p->geo, p->d_part, p->n_tiles, B, p->d_srt, rows, y, nullptr,
+                                                p->d_rs);
+    if ((rc = launch_check("row reduce"))) return rc;
+    if ((rc = run_adjoint_partials(p, B, st))) return rc;
+    const int splits = row_splits(p, B);
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, splits, (int)p->N, nullptr, s, eta / (float)B,
+                                                             alpha);
+    return launch_check("column reduce");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *spgm_last_error(void) { return g_last_error.c_str(); }
+
+int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mode) {
+    if (!out) return fail(SPGM_E_INVALID, "spgm_plan_create: out is NULL");
+    *out = nullptr;
+    if (!gm) return fail(SPGM_E_INVALID, "spgm_plan_create: geometry is NULL");
+    if (gm->n_tx < 1 || gm->n_rx < 1 || gm->n_freq < 1 || gm->nx < 1 || gm->ny < 1 || gm->nz < 1)
+        return fail(SPGM_E_INVALID, "spgm_plan_create: every count must be >= 1");
+    if (!gm->tx_xyz || !gm->rx_xyz || !gm->freq_hz)
+        return fail(SPGM_E_INVALID, "spgm_plan_create: tx_xyz, rx_xyz and freq_hz must be non-NULL");
+    if (phase_mode != SPGM_PHASE_COMP32 && phase_mode != SPGM_PHASE_F64 && phase_mode != SPGM_PHASE_NAIVE32)
+        return fail(SPGM_E_INVALID, "spgm_plan_create: unknown phase mode %d", phase_mode);
+    if (phase_mode != SPGM_PHASE_COMP32)
+        return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: phase mode %d is not built yet", phase_mode);
+    const int64_t T = gm->n_tx, R = gm->n_rx, F = gm->n_freq;
+    const int64_t M = F * T * R;
+    const int64_t N = (int64_t)gm->nx * gm->ny * gm->nz;
+    if (M > INT32_MAX || N > INT32_MAX) return fail(SPGM_E_INVALID, "spgm_plan_create: M or N exceeds 2^31-1");
+    if (std::min(T, R) > kMaxL || T + R > kMaxAnt)
+        return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: needs min(T,R) <= %d and T+R <= %d", kMaxL, kMaxAnt);
+    if (!(std::isfinite(gm->c) && gm->c > 0)) return fail(SPGM_E_INVALID, "spgm_plan_create: c must be finite and > 0");
+    if (!finite3(gm->centre) || !finite3(gm->pitch) || !(gm->pitch[0] > 0 && gm->pitch[1] > 0 && gm->pitch[2] > 0))
+        return fail(SPGM_E_INVALID, "spgm_plan_create: centre must be finite and pitch > 0");
+    for (int64_t f = 0; f < F; ++f) {
+        if (!(std::isfinite(gm->freq_hz[f]) && gm->freq_hz[f] > 0))
+            return fail(SPGM_E_INVALID, "spgm_plan_create: frequency %lld is not finite and > 0", (long long)f);
+        if (gm->pulse && !(std::isfinite(gm->pulse[2 * f]) && std::isfinite(gm->pulse[2 * f + 1])))
+            return fail(SPGM_E_INVALID, "spgm_plan_create: pulse %lld is not finite", (long long)f);
+    }
+    // Antenna positions; voxels must stay away from every antenna (Eq. 2 divides by distances).
+    const double lo[3] = {gm->centre[0] - 0.5 * (gm->nx - 1) * gm->pitch[0],
+                          gm->centre[1] - 0.5 * (gm->ny - 1) * gm->pitch[1],
+                          gm->centre[2] - 0.5 * (gm->nz - 1) * gm->pitch[2]};
+    const double hi[3] = {lo[0] + (gm->nx - 1) * gm->pitch[0], lo[1] + (gm->ny - 1) * gm->pitch[1],
+                          lo[2] + (gm->nz - 1) * gm->pitch[2]};
+    const int dims[3] = {gm->nx, gm->ny, gm->nz};
+    for (int64_t a = 0; a < T + R; ++a) {
+        const double *ra = a < T ? gm->tx_xyz + 3 * a : gm->rx_xyz + 3 * (a - T);
+        if (!finite3(ra)) return fail(SPGM_E_INVALID, "spgm_plan_create: antenna %lld is not finite", (long long)a);
+        double box = 0.0;  // distance from the antenna to the grid's bounding box
+        for (int k = 0; k < 3; ++k) {
+            const double dd = std::max(0.0, std::max(lo[k] - ra[k], ra[k] - hi[k]));
+            box += dd * dd;
+        }
+        if (std::sqrt(box) > 1e-9) continue;
+        // Antenna inside the box: test the nearest grid voxel.
+        double dmin2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double i = std::nearbyint((ra[k] - lo[k]) / gm->pitch[k]);
+            i = std::min<double>(std::max(i, 0.0), dims[k] - 1);
+            const double dd = lo[k] + i * gm->pitch[k] - ra[k];
+            dmin2 += dd * dd;
+        }
+        if (std::sqrt(dmin2) <= 1e-9)
+            return fail(SPGM_E_INVALID, "spgm_plan_create: antenna %lld coincides with a voxel", (long long)a);
+    }
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_create: no HIP device");
+    spgm_plan *p = new spgm_plan();
+    p->device = dev;
+    p->phase_mode = phase_mode;
+    p->M = M;
+    p->N = N;
+    Geo &g = p->geo;
+    g.T = (int)T;
+    g.R = (int)R;
+    g.F = (int)F;
+    g.nx = gm->nx;
+    g.ny = gm->ny;
+    g.nz = gm->nz;
+    g.nbx = (gm->nx + kBX - 1) / kBX;
+    g.nby = (gm->ny + kBY - 1) / kBY;
+    g.nbz = (gm->nz + kBZ - 1) / kBZ;
+    g.g_is_tx = R <= T ? 1 : 0;
+    g.nG = g.g_is_tx ? (int)T : (int)R;
+    g.nL = g.g_is_tx ? (int)R : (int)T;
+    g.cx = gm->centre[0];
+    g.cy = gm->centre[1];
+    g.cz = gm->centre[2];
+    g.px = gm->pitch[0];
+    g.py = gm->pitch[1];
+    g.pz = gm->pitch[2];
+    const int64_t tiles = (int64_t)g.nbx * g.nby * g.nbz;
+    p->n_tiles = (int)tiles;
+
+    double *ant = new double[3 * (T + R)];
+    std::memcpy(ant, gm->tx_xyz, sizeof(double) * 3 * T);
+    std::memcpy(ant + 3 * T, gm->rx_xyz, sizeof(double) * 3 * R);
+    double *kap = new double[F];
+    float2 *q = new float2[F];
+    const double inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
+    for (int64_t f = 0; f < F; ++f) {
+        kap[f] = gm->freq_hz[f] / gm->c;
+        const double pr = gm->pulse ? gm->pulse[2 * f] : 1.0;
+        const double pi = gm->pulse ? gm->pulse[2 * f + 1] : 0.0;
+        q[f] = make_float2((float)(pr * inv4pi), (float)(pi * inv4pi));
+    }
+    bool okk = hipMalloc(&p->d_ant, sizeof(double) * 3 * (T + R)) == hipSuccess &&
+               hipMalloc(&p->d_kappa, sizeof(double) * F) == hipSuccess &&
+               hipMalloc(&p->d_q, sizeof(float2) * F) == hipSuccess &&
+               hipMalloc(&p->d_status, sizeof(int)) == hipSuccess;
+    okk = okk && hipMemcpy(p->d_ant, ant, sizeof(double) * 3 * (T + R), hipMemcpyHostToDevice) == hipSuccess &&
+          hipMemcpy(p->d_kappa, kap, sizeof(double) * F, hipMemcpyHostToDevice) == hipSuccess &&
+          hipMemcpy(p->d_q, q, sizeof(float2) * F, hipMemcpyHostToDevice) == hipSuccess &&
+          hipMemset(p->d_status, 0, sizeof(int)) == hipSuccess;
+    delete[] ant;
+    delete[] kap;
+    delete[] q;
+    if (!okk) {
+        spgm_plan_destroy(p);
+        return fail(SPGM_E_NOMEM, "spgm_plan_create: device allocation or copy failed");
+    }
+    g.ant = p->d_ant;
+    g.kappa = p->d_kappa;
+    g.q = p->d_q;
+    const size_t A = (size_t)(T + R);
+    p->lds_bytes = (sizeof(double) + sizeof(float4)) * A + kSub * (sizeof(float) * 3 + sizeof(float2)) +
+                   std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * 4);
+    if (p->lds_bytes > 160 * 1024) {
+        spgm_plan_destroy(p);
+        return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: LDS footprint exceeds 160 KiB");
+    }
+    hipFuncSetAttribute((const void *)k_fwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
+    hipFuncSetAttribute((const void *)k_adj_tile, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
+    hipGetLastError();
+    *out = p;
+    return ok();
+}
+
+int spgm_plan_destroy(spgm_plan *p) {
+    if (!p) return ok();
+    DeviceGuard guard(p->device);
+    hipDeviceSynchronize();
+    hipFree(p->d_ant);
+    hipFree(p->d_kappa);
+    hipFree(p->d_q);
+    hipFree(p->d_status);
+    hipFree(p->d_srt);
+    hipFree(p->d_part);
+    hipFree(p->d_rs);
+    hipFree(p->d_gpart);
+    delete p;
+    return ok();
+}
+
+int spgm_plan_dims(const spgm_plan *p, int64_t *M, int64_t *N) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm_plan_dims: plan is NULL");
+    if (M) *M = p->M;
+    if (N) *N = p->N;
+    return ok();
+}
+
+int spgm_forward(spgm_plan *p, const int32_t *rows, int32_t B, const void *s, void *y, void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if (!s || !y) return fail(SPGM_E_INVALID, "spgm_forward: s and y must be non-NULL");
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, st))) return rc;
+    if ((rc = run_forward_partials(p, (const float2 *)s, B, st))) return rc;
+    k_row_reduce<<<(B + 63) / 64, 256, 0, st>>>(p->geo, p->d_part, p->n_tiles, B, p->d_srt, rows, nullptr,
+                                                (float2 *)y, nullptr);
+    if ((rc = launch_check("row reduce"))) return rc;
+    return ok();
+}
+
+int spgm_adjoint(spgm_plan *p, const int32_t *rows, int32_t B, const void *r, void *g, void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if (!r || !g) return fail(SPGM_E_INVALID, "spgm_adjoint: r and g must be non-NULL");
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, st))) return rc;
+    k_gather_scale<<<(B + 255) / 256, 256, 0, st>>>(p->geo, p->d_srt, B, (const float2 *)r, p->d_rs);
+    if ((rc = launch_check("gather"))) return rc;
+    if ((rc = run_adjoint_partials(p, B, st))) return rc;
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, row_splits(p, B), (int)p->N, (float2 *)g,
+                                                             nullptr, 0.f, 0.f);
+    if ((rc = launch_check("column reduce"))) return rc;
+    return ok();
+}
+
+static int check_step_args(const void *y, const void *s, float eta, float alpha) {
+    if (!y || !s) return fail(SPGM_E_INVALID, "spgm: y and s must be non-NULL");
+    if (!(std::isfinite(eta) && eta > 0)) return fail(SPGM_E_INVALID, "spgm: eta must be finite and > 0");
+    if (!(std::isfinite(alpha) && alpha >= 0)) return fail(SPGM_E_INVALID, "spgm: alpha must be finite and >= 0");
+    return SPGM_OK;
+}
+
+int spgm_step(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, void *s, float eta, float alpha,
+              void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B))) return rc;
+    if ((rc = step_impl(p, rows, B, (const float2 *)y, (float2 *)s, eta, alpha, (hipStream_t)stream))) return rc;
+    return ok();
+}
+
+int spgm_solve(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, const void *y, void *s, float eta,
+               float alpha, void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve: iters must be >= 0");
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B))) return rc;
+    for (int k = 0; k < iters; ++k) {
+        if ((rc = step_impl(p, rows + (size_t)k * B, B, (const float2 *)y, (float2 *)s, eta, alpha,
+                            (hipStream_t)stream)))
+            return rc;
+    }
+    return ok();
+}
+
+int spgm_plan_status(spgm_plan *p, int32_t *status) {
+    if (!p || !status) return fail(SPGM_E_INVALID, "spgm_plan_status: plan and status must be non-NULL");
+    DeviceGuard guard(p->device);
+    int h = 0;
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(&h, p->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemset(p->d_status, 0, sizeof(int)) != hipSuccess)
+        return fail(SPGM_E_DEVICE, "spgm_plan_status: device error");
+    *status = h ? SPGM_E_BADROW : SPGM_OK;
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+"""Write ``step_sizes.json``: the Lipschitz estimate L of the minibatch gradient per workload.
+
+For each workload, L = max over a few seeded minibatches of the largest eigenvalue of
+A_B^H A_B / B, by power iteration with the FP64 oracle.  The solver uses eta = 1/L (Sec. IV:
+a proximal-gradient step size at most the inverse Lipschitz constant of the data-fidelity
+gradient) and lambda = 0.05 * max|A^H y| / M.  The synthetic measurements y come from the
+oracle as well (forward projection of the seeded scene plus seeded noise).
+
+Calls only the oracle and the seeded input generators.  Usage:
+    python tests/golden/make_step_sizes.py [workload ...]
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+from oracle import Oracle  # noqa: E402
+from paper_2509_00774_amd import workloads as W  # noqa: E402
+
+# workload -> (minibatches, power iterations)
+PLAN = {"c0": (8, 100), "c4": (4, 40), "c1": (1, 10)}
+OUT = os.path.join(HERE, "step_sizes.json")
+
+
+def measurements(name, orc):
+    s, idx = W.config_scene(name)
+    cfg = W.CONFIGS[name]
+    y0 = orc.forward_sparse(np.arange(orc.M), idx, s[idx])
+    return W.add_noise(y0, cfg["snr_db"], seed=cfg["seed"] + 2)
+
+
+def main(names):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in names:
+        t0 = time.time()
+        cfg = W.CONFIGS[name]
+        orc = Oracle(W.config_geometry(name))
+        nb, iters = PLAN[name]
+        rows = W.draw_rows(orc.M, cfg["B"], nb, seed=cfg["seed"] + 5)
+        Ls = [orc.lipschitz(rows[k], iters=iters, seed=k) for k in range(nb)]
+        y = measurements(name, orc)
+        lam_max = orc.lambda_max(y)
+        data[name] = {"L": max(Ls), "L_per_batch": Ls, "power_iters": iters, "lambda_max": lam_max,
+                      "eta": 1.0 / max(Ls), "lambda": 0.05 * lam_max,
+                      "note": "L = max over seeded minibatches of lambda_max(A_B^H A_B)/B (FP64 power "
+                              "iteration); lambda_max = max|A^H y|/M with y from the oracle"}
+        print(name, data[name], "%.1fs" % (time.time() - t0), flush=True)
+        json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["c0", "c4", "c1"])

@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs.
+
+Tolerance (float32 projector, compensated phase): relative L2 error <= 1e-5 of every output
+vector; elementwise |gpu - oracle| <= 1e-4 * max|oracle| as a per-element guard.  The SPGM
+iterate after a full solve is held to the same 1e-5 relative L2 bound.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, rel_l2
+from paper_2509_00774_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+ELEM = 1e-4
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def bd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_00774_amd import binding
+    binding.load_library()
+    return binding
+
+
+def cdev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.complex64))).cuda()
+
+
+def idev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.int32))).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def check(got, ref, what):
+    err = rel_l2(got, ref)
+    emax = np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)
+    say("%s: rel_l2=%.3e elem_max=%.3e" % (what, err, emax))
+    assert err <= TOL, (what, err)
+    assert emax <= ELEM, (what, emax)
+
+
+def projector_case(bd, geom, rows, seed, what):
+    orc = Oracle(geom)
+    plan = bd.Plan(geom)
+    s = W.random_complex(orc.N, seed=seed)
+    r = W.random_complex(len(rows), seed=seed + 1)
+    y_gpu = host(plan.forward(idev(rows), cdev(s)))
+    g_gpu = host(plan.adjoint(idev(rows), cdev(r)))
+    # the oracle sees the same complex64-rounded inputs
+    s64 = s.astype(np.complex64).astype(np.complex128)
+    r64 = r.astype(np.complex64).astype(np.complex128)
+    check(y_gpu, orc.forward(rows, s64), what + " forward")
+    check(g_gpu, orc.adjoint(rows, r64), what + " adjoint")
+    assert plan.status() == 0
+    plan.close()
+
+
+def test_c0_projector(bd):
+    geom = W.config_geometry("c0")
+    rows = W.config_rows("c0", K=1)[0]
+    projector_case(bd, geom, rows, 100, "c0")
+
+
+@pytest.mark.parametrize("T,R,F,grid,B", [
+    (5, 7, 6, (13, 11, 6), 37),     # R > T (roles of the two arrays swapped), ragged bricks
+    (9, 3, 4, (8, 8, 4), 1),        # a single row
+    (6, 6, 3, (17, 9, 5), 108),     # every row of the matrix
+    (2, 1, 1, (3, 2, 1), 2),        # smallest grid, one brick mostly empty
+])
+def test_ragged_shapes(bd, T, R, F, grid, B):
+    pulse = np.exp(1j * np.linspace(0, 2, F)) * np.linspace(1.0, 0.4, F)
+    geom = W.make_geometry(T, R, F, (20e9, 30e9), grid, 4e-3, 0.22, 0.2, pulse=pulse, seed=T * 100 + R)
+    M = F * T * R
+    rng = np.random.default_rng(B)
+    rows = np.arange(M) if B == M else rng.integers(0, M, size=B)  # repeats allowed
+    projector_case(bd, geom, rows.astype(np.int32), 200 + B, "ragged T%d R%d grid%s B%d" % (T, R, grid, B))
+
+
+def test_duplicate_rows_count_twice(bd):
+    geom = W.make_geometry(4, 4, 4, (20e9, 30e9), (8, 8, 4), 5e-3, 0.25, 0.2, seed=3)
+    plan = bd.Plan(geom)
+    s = cdev(W.random_complex(plan.N, seed=4))
+    y1 = host(plan.forward(idev([5, 5, 9]), s))
+    assert y1[0] == y1[1]
+    r = cdev(np.array([1.0 + 2j, -0.5j, 0.25]))
+    g_dup = host(plan.adjoint(idev([5, 5, 9]), r))
+    g_one = host(plan.adjoint(idev([5, 9]), cdev(np.array([1.0 + 1.5j, 0.25]))))
+    assert rel_l2(g_dup, g_one) < 1e-6
+
+
+def test_bad_row_sets_sticky_status(bd):
+    geom = W.make_geometry(4, 4, 4, (20e9, 30e9), (8, 8, 4), 5e-3, 0.25, 0.2, seed=3)
+    plan = bd.Plan(geom)
+    s = cdev(W.random_complex(plan.N, seed=4))
+    plan.forward(idev([0, 1, plan.M]), s)  # M is out of range
+    assert plan.status() == bd.SPGM_E_BADROW
+    assert plan.status() == 0  # cleared by the read
+
+
+def test_bitwise_reproducible(bd):
+    geom = W.config_geometry("c0")
+    plan = bd.Plan(geom)
+    rows = idev(W.config_rows("c0", K=1)[0])
+    s = cdev(W.random_complex(plan.N, seed=5))
+    a = host(plan.forward(rows, s))
+    b = host(plan.forward(rows, s))
+    assert np.array_equal(a, b)
+    r = cdev(W.random_complex(rows.numel(), seed=6))
+    assert np.array_equal(host(plan.adjoint(rows, r)), host(plan.adjoint(rows, r)))
+
+
+def test_adjoint_identity_fp32(bd):
+    geom = W.config_geometry("c0")
+    plan = bd.Plan(geom)
+    rows = idev(W.config_rows("c0", K=1)[0])
+    s = W.random_complex(plan.N, seed=7).astype(np.complex64)
+    r = W.random_complex(rows.numel(), seed=8).astype(np.complex64)
+    As = host(plan.forward(rows, cdev(s)))
+    Ahr = host(plan.adjoint(rows, cdev(r)))
+    lhs = np.vdot(r.astype(np.complex128), As)
+    rhs = np.vdot(Ahr, s.astype(np.complex128))
+    assert abs(lhs - rhs) / (np.linalg.norm(As) * np.linalg.norm(r)) < 1e-5
+
+
+def c0_problem():
+    cfg = W.CONFIGS["c0"]
+    geom = W.config_geometry("c0")
+    orc = Oracle(geom)
+    s_true, idx = W.config_scene("c0")
+    y = W.add_noise(orc.forward_sparse(np.arange(orc.M), idx, s_true[idx]), cfg["snr_db"], seed=cfg["seed"] + 2)
+    y = y.astype(np.complex64).astype(np.complex128)
+    lam = 0.05 * orc.lambda_max(y)
+    L = max(orc.lipschitz(r, iters=60, seed=k) for k, r in enumerate(W.draw_rows(orc.M, cfg["B"], 4, seed=77)))
+    eta = np.float32(1.0 / L)
+    alpha = np.float32(lam * float(eta))
+    return geom, orc, y, s_true, float(eta), float(alpha)
+
+
+def test_c0_step_and_solve(bd):
+    geom, orc, y, s_true, eta, alpha = c0_problem()
+    plan = bd.Plan(geom)
+    rows = W.config_rows("c0")  # 200 x 256
+    # one step from a non-zero iterate
+    s0 = W.random_complex(orc.N, seed=9).astype(np.complex64)
+    s_gpu = cdev(s0)
+    plan.step(idev(rows[0]), cdev(y), s_gpu, eta, alpha)
+    check(host(s_gpu), orc.step(rows[0], y, s0.astype(np.complex128), eta, alpha), "c0 step")
+    # the full 200-iteration SPGM solve from zero
+    s_gpu = torch.zeros(orc.N, dtype=torch.complex64, device="cuda")
+    plan.solve(idev(rows), cdev(y), s_gpu, eta, alpha)
+    s_ref = orc.solve(rows, y, np.zeros(orc.N), eta, alpha)
+    got = host(s_gpu)
+    check(got, s_ref, "c0 solve K=200")
+    say("c0 solve: nnz gpu %d oracle %d, NMSE vs truth %.3e" % (
+        np.count_nonzero(got), np.count_nonzero(s_ref), np.sum(np.abs(got - s_true) ** 2) / np.sum(np.abs(s_true) ** 2)))
+    assert plan.status() == 0
+
+
+def test_c1_full_size_sampled(bd):
+    """Full c1 launch (B = 4096, N = 131072); the oracle evaluates 24 rows and 96 voxels."""
+    geom = W.config_geometry("c1")
+    orc = Oracle(geom)
+    plan = bd.Plan(geom)
+    rows = W.config_rows("c1", K=1)[0]
+    s = W.random_complex(orc.N, seed=21).astype(np.complex64)
+    r = W.random_complex(rows.size, seed=22).astype(np.complex64)
+    y_gpu = host(plan.forward(idev(rows), cdev(s)))
+    g_gpu = host(plan.adjoint(idev(rows), cdev(r)))
+    rng = np.random.default_rng(23)
+    js = np.sort(rng.choice(rows.size, 24, replace=False))
+    vs = np.sort(rng.choice(orc.N, 96, replace=False))
+    check(y_gpu[js], orc.forward(rows[js], s.astype(np.complex128)), "c1 forward (24 sampled rows)")
+    check(g_gpu[vs], orc.adjoint_voxels(rows, r.astype(np.complex128), vs), "c1 adjoint (96 sampled voxels)")

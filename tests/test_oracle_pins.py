@@ -312,3 +312,12 @@ def test_solve_equals_repeated_steps_and_resumes():
     assert np.array_equal(full, s)
     half = orc.solve(rows[:3], y, s0, 0.01, 0.001)
     assert np.array_equal(orc.solve(rows[3:], y, half, 0.01, 0.001), full)
+
+
+def test_adjoint_voxel_subset_matches_full_adjoint():
+    geom = small_geom(seed=91)
+    orc = Oracle(geom)
+    rows = W.draw_rows(orc.M, 20, 1, seed=92)[0]
+    r = W.random_complex(rows.size, seed=93)
+    idx = np.array([0, 5, 17, orc.N - 1])
+    assert np.array_equal(orc.adjoint_voxels(rows, r, idx), orc.adjoint(rows, r)[idx])
