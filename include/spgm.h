@@ -74,7 +74,7 @@ typedef struct spgm_plan spgm_plan;
 /* Create a plan for `geom` on the current HIP device (Sec. II, Eq. 2 defines what it encodes).
  * Rejects (SPGM_E_INVALID): null pointers, any count < 1, M or N above 2^31 - 1, pitch or c or a
  * frequency <= 0, a non-finite value, or a voxel closer than 1e-9 m to an antenna (Eq. 2 is
- * singular there).  SPGM_E_UNSUPPORTED: min(T, R) > 64 or max(T, R) > 4096.  On success
+ * singular there).  SPGM_E_UNSUPPORTED: min(T, R) > 64 or T + R > 512.  On success
  * *out owns device memory released by spgm_plan_destroy.  Synchronous. */
 int spgm_plan_create(spgm_plan **out, const spgm_geometry *geom, int32_t phase_mode);
 
@@ -113,6 +113,15 @@ int spgm_solve(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B,
 /* Device-detected errors of earlier calls (currently SPGM_E_BADROW).  Synchronises the plan's
  * device, writes the sticky status to *status (SPGM_OK if none) and clears it. */
 int spgm_plan_status(spgm_plan *plan, int32_t *status);
+
+/* Kernel timing instrumentation.  While enabled, every launch of the two entry-generating
+ * kernels (forward tile, adjoint tile) is bracketed by HIP events recorded on the call's
+ * stream.  spgm_plan_timing_read synchronises the plan's device, returns the summed kernel
+ * durations (milliseconds) and launch counts since the last read, and resets them.  Any
+ * output pointer may be NULL. */
+int spgm_plan_timing(spgm_plan *plan, int32_t enable);
+int spgm_plan_timing_read(spgm_plan *plan, double *fwd_ms, int64_t *fwd_launches, double *adj_ms,
+                          int64_t *adj_launches);
 
 /* Message describing the last failure of a call on this thread ("" if none). */
 const char *spgm_last_error(void);

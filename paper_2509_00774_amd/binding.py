@@ -28,7 +28,8 @@ PHASE_F64 = 1
 PHASE_NAIVE32 = 2
 
 EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
-            "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error")
+            "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
+            "spgm_plan_timing_read")
 
 _dp = C.POINTER(C.c_double)
 
@@ -70,6 +71,9 @@ def load_library(path: str = LIB_PATH):
         "spgm_step": [vp, vp, i32, vp, vp, f32, f32, vp],
         "spgm_solve": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_plan_status": [vp, C.POINTER(i32)],
+        "spgm_plan_timing": [vp, i32],
+        "spgm_plan_timing_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_int64)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -207,6 +211,16 @@ class Plan:
         st = C.c_int32()
         _check(self._lib.spgm_plan_status(self._h, C.byref(st)))
         return st.value
+
+    def spgm_plan_timing(self, enable=True):
+        _check(self._lib.spgm_plan_timing(self._h, 1 if enable else 0))
+
+    def spgm_plan_timing_read(self):
+        """(forward-tile ms, launches, adjoint-tile ms, launches) since the last read."""
+        fm, am = C.c_double(), C.c_double()
+        fn, an = C.c_int64(), C.c_int64()
+        _check(self._lib.spgm_plan_timing_read(self._h, C.byref(fm), C.byref(fn), C.byref(am), C.byref(an)))
+        return fm.value, fn.value, am.value, an.value
 
     # short aliases
     forward = spgm_forward

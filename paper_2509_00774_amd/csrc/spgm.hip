@@ -39,6 +39,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "spgm.h"
 
@@ -575,6 +576,10 @@ struct spgm_plan {
     float2 *d_rs = nullptr;
     float2 *d_gpart = nullptr;
     size_t lds_bytes = 0;
+    // kernel timing instrumentation
+    bool timing = false;
+    std::vector<hipEvent_t> ev_fwd, ev_adj;  // pairs: [2k] start, [2k+1] stop
+    size_t n_fwd = 0, n_adj = 0;
 };
 
 namespace {
@@ -633,18 +638,40 @@ int run_sort(spgm_plan *p, const int32_t *rows, int B, hipStream_t st) {
     return launch_check("sort");
 }
 
+// Start/stop events of the next timed launch, growing the pool as needed (nullptr if off).
+hipEvent_t *timing_slot(spgm_plan *p, std::vector<hipEvent_t> &pool, size_t &used) {
+    if (!p->timing) return nullptr;
+    if (2 * used + 2 > pool.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&b) != hipSuccess) {
+            hipEventDestroy(a);
+            return nullptr;
+        }
+        pool.push_back(a);
+        pool.push_back(b);
+    }
+    return &pool[2 * used++];
+}
+
 int run_forward_partials(spgm_plan *p, const float2 *s, int B, hipStream_t st) {
     const int splits = row_splits(p, B);
     const int rpw = (B + splits - 1) / splits;
+    hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
+    if (ev) hipEventRecord(ev[0], st);
     k_fwd_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, p->d_srt, B, rpw, s, p->d_part);
+    if (ev) hipEventRecord(ev[1], st);
     return launch_check("forward");
 }
 
 int run_adjoint_partials(spgm_plan *p, int B, hipStream_t st) {
     const int splits = row_splits(p, B);
     const int rpw = (B + splits - 1) / splits;
+    hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
+    if (ev) hipEventRecord(ev[0], st);
     k_adj_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, p->d_srt, B, rpw, p->d_rs,
                                                                         p->d_gpart, (int)p->N);
+    if (ev) hipEventRecord(ev[1], st);
     return launch_check("adjoint");
 }
 
@@ -809,6 +836,8 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_part);
     hipFree(p->d_rs);
     hipFree(p->d_gpart);
+    for (hipEvent_t e : p->ev_fwd) hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_adj) hipEventDestroy(e);
     delete p;
     return ok();
 }
@@ -894,6 +923,32 @@ int spgm_plan_status(spgm_plan *p, int32_t *status) {
         hipMemset(p->d_status, 0, sizeof(int)) != hipSuccess)
         return fail(SPGM_E_DEVICE, "spgm_plan_status: device error");
     *status = h ? SPGM_E_BADROW : SPGM_OK;
+    return ok();
+}
+
+int spgm_plan_timing(spgm_plan *p, int32_t enable) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm_plan_timing: plan is NULL");
+    p->timing = enable != 0;
+    return ok();
+}
+
+int spgm_plan_timing_read(spgm_plan *p, double *fwd_ms, int64_t *fwd_n, double *adj_ms, int64_t *adj_n) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm_plan_timing_read: plan is NULL");
+    DeviceGuard guard(p->device);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_timing_read: device error");
+    auto total = [](const std::vector<hipEvent_t> &pool, size_t used) {
+        double ms = 0.0;
+        for (size_t k = 0; k < used; ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) ms += t;
+        }
+        return ms;
+    };
+    if (fwd_ms) *fwd_ms = total(p->ev_fwd, p->n_fwd);
+    if (adj_ms) *adj_ms = total(p->ev_adj, p->n_adj);
+    if (fwd_n) *fwd_n = (int64_t)p->n_fwd;
+    if (adj_n) *adj_n = (int64_t)p->n_adj;
+    p->n_fwd = p->n_adj = 0;
     return ok();
 }
 
