@@ -74,18 +74,45 @@ struct Geo {
 // Device helpers
 // ------------------------------------------------------------------------------------------
 
-// Sum over the 64 lanes of a wave with DPP row operations; the total lands in lane 63.
-__device__ __forceinline__ float wave_sum_to_63(float v) {
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x140, 0xF, 0xF, true);  // row_mirror
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x142, 0xA, 0xF, false); // row_bcast:15
-    v += __builtin_amdgcn_update_dpp(0.0f, v, 0x143, 0xC, 0xF, false); // row_bcast:31
-    return v;
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Sum sixteen per-lane values x[q] (one per row q) over the 64 lanes of a wave at once.  Each
+// halving step swaps half of the lanes between two registers and adds, so that the number of
+// live registers halves while the lanes summed into each doubles (32-lane and 16-lane swaps,
+// then an 8-lane rotation and a 4-lane mirror inside each 16-lane row, then a quad sum).  On
+// return lane l holds the total of row l >> 2.  b3, b2: bits 3 and 2 of the lane index.
+__device__ __forceinline__ float wave_transpose_sum16(const float (&x)[16], bool b3, bool b2) {
+    float y[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[j]), __float_as_uint(x[j + 8]), false, false);
+        y[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // lanes 0-31: row j, 32-63: row j+8
+    }
+    float z[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y[j]), __float_as_uint(y[j + 4]), false, false);
+        z[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // 16-lane group g: row j + 4g
+    }
+    float w[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float t1 = b3 ? z[j + 2] : z[j];
+        const float t2 = b3 ? z[j] : z[j + 2];
+        w[j] = t1 + dpp_f<0x128>(t2);  // row_ror:8; bit3 = 0: row j + 4g, bit3 = 1: row j + 2 + 4g
+    }
+    const float t1 = b2 ? w[1] : w[0];
+    const float t2 = b2 ? w[0] : w[1];
+    float v = t1 + dpp_f<0x141>(t2);   // row_half_mirror; row 4g + 2 bit3 + bit2 = l >> 2
+    v += dpp_f<0xB1>(v);                // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);                // quad_perm [2,3,0,1]
+    return v;
+}
 
 // Brick decomposition of a tile index.
 __device__ __forceinline__ void brick_of(const Geo &g, int tile, int &bx, int &by, int &bz) {
@@ -132,7 +159,9 @@ __device__ __forceinline__ int ant_of_l(const Geo &g, int li) { return g.g_is_tx
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kSortThreads) void k_sort_rows(Geo g, const int32_t *__restrict__ rows, int B,
                                                             int4 *__restrict__ srt, int *__restrict__ status) {
-    __shared__ unsigned long long keys[kSortChunk];
+    extern __shared__ unsigned long long keys[];  // next power of two >= min(B, kSortChunk)
+    rows += (size_t)blockIdx.y * B;               // minibatch blockIdx.y of a batched sort
+    srt += (size_t)blockIdx.y * B;
     const int c0 = blockIdx.x * kSortChunk;
     const int n = min(kSortChunk, B - c0);
     int p2 = 2;
@@ -190,10 +219,8 @@ struct TileSmem {
     float4 *antg;   // [T+R]: (c - r_a) float32, |c - r_a| float32
     double *antd;   // [T+R]: |c - r_a| float64
     float2 *lside;  // [nL][256]: (delta, w) per L antenna per brick voxel
-    float *kap;     // [kSub]
-    float *ref;     // [kSub]
-    int *gl;        // [kSub]: G index | L index << 16
-    float2 *rowv;   // [kSub]: forward row sums / adjoint scaled residuals
+    float4 *rowinfo; // [kSub]: (kappa, reference phase, G index | L index << 16 as bits, 0)
+    float2 *rowv;    // [kSub]: forward row sums / adjoint scaled residuals
 };
 
 __device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
@@ -202,10 +229,9 @@ __device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
     t.antg = reinterpret_cast<float4 *>(smem);
     t.antd = reinterpret_cast<double *>(smem + sizeof(float4) * A);
     char *p = smem + (sizeof(double) + sizeof(float4)) * A;
-    t.kap = reinterpret_cast<float *>(p);
-    t.ref = t.kap + kSub;
-    t.gl = reinterpret_cast<int *>(t.ref + kSub);
-    t.rowv = reinterpret_cast<float2 *>(t.gl + kSub);
+    p += (16 - reinterpret_cast<uintptr_t>(p) % 16) % 16;
+    t.rowinfo = reinterpret_cast<float4 *>(p);
+    t.rowv = reinterpret_cast<float2 *>(t.rowinfo + kSub);
     t.lside = t.rowv + kSub;
     return t;
 }
@@ -223,12 +249,14 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int
     }
     __syncthreads();
     const int v = threadIdx.x;  // brick voxel: lane -> (x, y), wave -> z
+    const int lx = (v & 63) & 7, ly = (v & 63) >> 3, lz = v >> 6;
+    const bool inside = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + lz < g.nz;
     float ex, ey, ez;
-    local_offset(g, (v & 63) & 7, (v & 63) >> 3, v >> 6, ex, ey, ez);
+    local_offset(g, lx, ly, lz, ex, ey, ez);
     for (int li = 0; li < g.nL; ++li) {
-        float dl, wl;
-        comp_offset(ex, ey, ez, sm.antg[ant_of_l(g, li)], dl, wl);
-        sm.lside[li * kBrick + v] = make_float2(dl, wl);
+        float dl = 0.f, wl = 0.f;
+        if (inside) comp_offset(ex, ey, ez, sm.antg[ant_of_l(g, li)], dl, wl);
+        sm.lside[li * kBrick + v] = make_float2(dl, wl);  // voxels outside the grid contribute 0
     }
 }
 
@@ -242,9 +270,7 @@ __device__ __forceinline__ void stage_rows(const Geo &g, const TileSmem &sm, con
         const double kap = g.kappa[info.y];
         double ph = kap * (sm.antd[ant_of_g(g, info.z)] + sm.antd[ant_of_l(g, info.w)]);
         ph -= rint(ph);
-        sm.kap[k] = (float)kap;
-        sm.ref[k] = (float)ph;
-        sm.gl[k] = info.z | (info.w << 16);
+        sm.rowinfo[k] = make_float4((float)kap, (float)ph, __int_as_float(info.z | (info.w << 16)), 0.f);
     }
 }
 
@@ -283,6 +309,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
 #pragma unroll
     for (int p = 0; p < kP; ++p) dG[p] = usr[p] = usi[p] = D[p] = ur[p] = ui[p] = 0.f;
     int cur_g = -1, cur_l = -1;
+    const bool b3 = lane & 8, b2 = lane & 4;
 
     for (int base = r0; base < r1; base += kSub) {
         const int nsub = min(kSub, r1 - base);
@@ -291,47 +318,65 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
         __syncthreads();
         const int kb = wave * kWave;
         const int ke = min(nsub, kb + kWave);
-        for (int k = kb; k < ke; ++k) {
-            const int gl = uniform(sm.gl[k]);
-            const int gi = gl & 0xffff, li = gl >> 16;
-            if (gi != cur_g) {
-                const float4 ga = sm.antg[ant_of_g(g, gi)];
+        // Blocks of up to 16 rows that share the G antenna; one transposed reduction per block.
+        for (int k0 = kb; k0 < ke;) {
+            const int g0 = uniform(__float_as_int(sm.rowinfo[k0].z)) & 0xffff;
+            if (g0 != cur_g) {
+                const float4 ga = sm.antg[ant_of_g(g, g0)];
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
-                    float wg;
-                    comp_offset(ex[p], ey[p], ez[p], ga, dG[p], wg);
+                    float dg, wg;
+                    comp_offset(ex[p], ey[p], ez[p], ga, dg, wg);
+                    dG[p] = valid[p] ? dg : 0.f;
                     usr[p] = valid[p] ? wg * sr[p] : 0.f;
                     usi[p] = valid[p] ? wg * si[p] : 0.f;
                 }
-                cur_g = gi;
+                cur_g = g0;
                 cur_l = -1;
             }
-            if (li != cur_l) {
+            // block length: rows k0 .. k0+len-1 all use G antenna g0
+            const int q = lane & 15;
+            const int kq = k0 + q;
+            const bool other = kq >= ke || ((__float_as_int(sm.rowinfo[min(kq, ke - 1)].z) & 0xffff) != g0);
+            const unsigned long long stop = __ballot(other) & 0xffffull;
+            const int len = stop ? __ffsll((long long)stop) - 1 : 16;
+            float accr[16], acci[16];
 #pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    const float2 lv = sm.lside[li * kBrick + p * kWave + lane];
-                    D[p] = valid[p] ? dG[p] + lv.x : 0.f;
-                    ur[p] = valid[p] ? lv.y * usr[p] : 0.f;
-                    ui[p] = valid[p] ? lv.y * usi[p] : 0.f;
+            for (int qq = 0; qq < 16; ++qq) {
+                float ar = 0.f, ai = 0.f;
+                if (qq < len) {
+                    const float4 ri = sm.rowinfo[k0 + qq];
+                    const int li = uniform(__float_as_int(ri.z)) >> 16;
+                    if (li != cur_l) {
+#pragma unroll
+                        for (int p = 0; p < kP; ++p) {
+                            const float2 lv = sm.lside[li * kBrick + p * kWave + lane];
+                            D[p] = dG[p] + lv.x;
+                            ur[p] = lv.y * usr[p];
+                            ui[p] = lv.y * usi[p];
+                        }
+                        cur_l = li;
+                    }
+#pragma unroll
+                    for (int p = 0; p < kP; ++p) {
+                        const float ph = fmaf(ri.x, D[p], ri.y);
+                        const float sn = __builtin_amdgcn_sinf(ph);
+                        const float cs = __builtin_amdgcn_cosf(ph);
+                        // (cs - j sn)(ur + j ui)
+                        ar = fmaf(cs, ur[p], ar);
+                        ar = fmaf(sn, ui[p], ar);
+                        ai = fmaf(cs, ui[p], ai);
+                        ai = fmaf(-sn, ur[p], ai);
+                    }
                 }
-                cur_l = li;
+                accr[qq] = ar;
+                acci[qq] = ai;
             }
-            const float kap = sm.kap[k], ref = sm.ref[k];
-            float ar = 0.f, ai = 0.f;
-#pragma unroll
-            for (int p = 0; p < kP; ++p) {
-                const float ph = fmaf(kap, D[p], ref);
-                const float sn = __builtin_amdgcn_sinf(ph);
-                const float cs = __builtin_amdgcn_cosf(ph);
-                // (cs - j sn)(ur + j ui)
-                ar = fmaf(cs, ur[p], ar);
-                ar = fmaf(sn, ui[p], ar);
-                ai = fmaf(cs, ui[p], ai);
-                ai = fmaf(-sn, ur[p], ai);
-            }
-            ar = wave_sum_to_63(ar);
-            ai = wave_sum_to_63(ai);
-            if (lane == 63) sm.rowv[k] = make_float2(ar, ai);
+            const float tr = wave_transpose_sum16(accr, b3, b2);
+            const float ti = wave_transpose_sum16(acci, b3, b2);
+            const int row = lane >> 2;
+            if ((lane & 3) == 0 && row < len) sm.rowv[k0 + row] = make_float2(tr, ti);
+            k0 += len;
         }
         __syncthreads();
         if ((int)threadIdx.x < nsub) part[(size_t)tile * B + base + threadIdx.x] = sm.rowv[threadIdx.x];
@@ -342,16 +387,20 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
 // 3. Row reduction: v_i = q_f * sum_tiles part[tile][i]  (minus y_m when y is given).
 //    out_user[j] = v (caller order); out_scaled[i] = conj(q_f) * v (sorted order, adjoint input).
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_row_reduce(Geo g, const float2 *__restrict__ part, int n_tiles, int B,
-                                                    const int4 *__restrict__ srt, const int32_t *__restrict__ rows,
-                                                    const float2 *__restrict__ y, float2 *__restrict__ out_user,
-                                                    float2 *__restrict__ out_scaled) {
-    __shared__ float2 red[4][64];
+constexpr int kRedGroups = 16;  // tile groups per row-reduction work-group (64 rows x 16)
+
+__global__ __launch_bounds__(64 * kRedGroups) void k_row_reduce(Geo g, const float2 *__restrict__ part, int n_tiles,
+                                                               int B, const int4 *__restrict__ srt,
+                                                               const int32_t *__restrict__ rows,
+                                                               const float2 *__restrict__ y,
+                                                               float2 *__restrict__ out_user,
+                                                               float2 *__restrict__ out_scaled) {
+    __shared__ float2 red[kRedGroups][64];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + tx;
     float ar = 0.f, ai = 0.f;
     if (i < B) {
-        for (int t = ty; t < n_tiles; t += 4) {
+        for (int t = ty; t < n_tiles; t += kRedGroups) {
             const float2 v = part[(size_t)t * B + i];
             ar += v.x;
             ai += v.y;
@@ -360,8 +409,12 @@ __global__ __launch_bounds__(256) void k_row_reduce(Geo g, const float2 *__restr
     red[ty][tx] = make_float2(ar, ai);
     __syncthreads();
     if (ty == 0 && i < B) {
-        ar = red[0][tx].x + red[1][tx].x + red[2][tx].x + red[3][tx].x;
-        ai = red[0][tx].y + red[1][tx].y + red[2][tx].y + red[3][tx].y;
+        ar = red[0][tx].x;
+        ai = red[0][tx].y;
+        for (int k = 1; k < kRedGroups; ++k) {
+            ar += red[k][tx].x;
+            ai += red[k][tx].y;
+        }
         const int4 info = srt[i];
         const float2 q = g.q[info.y];
         float vr = q.x * ar - q.y * ai;
@@ -411,8 +464,12 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
     const int wave = threadIdx.x >> 6;
     const int lx = lane & 7, ly = lane >> 3;
     float ex[kP], ey[kP], ez[kP];
+    bool valid[kP];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
+    for (int p = 0; p < kP; ++p) {
+        local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
+        valid[p] = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + p < g.nz;
+    }
 
     float dG[kP], wG[kP], D[kP], W[kP], hr[kP], hi[kP], gr[kP], gi_[kP];
 #pragma unroll
@@ -428,7 +485,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
         const int kb = wave * kWave;
         const int ke = min(nsub, kb + kWave);
         for (int k = kb; k < ke; ++k) {
-            const int gl = uniform(sm.gl[k]);
+            const float4 ri = sm.rowinfo[k];
+            const int gl = uniform(__float_as_int(ri.z));
             const int gi = gl & 0xffff, li = gl >> 16;
             if (gi != cur_g || li != cur_l) {
 #pragma unroll
@@ -440,7 +498,12 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
                 if (gi != cur_g) {
                     const float4 ga = sm.antg[ant_of_g(g, gi)];
 #pragma unroll
-                    for (int p = 0; p < kP; ++p) comp_offset(ex[p], ey[p], ez[p], ga, dG[p], wG[p]);
+                    for (int p = 0; p < kP; ++p) {
+                        float dg, wg;
+                        comp_offset(ex[p], ey[p], ez[p], ga, dg, wg);
+                        dG[p] = valid[p] ? dg : 0.f;
+                        wG[p] = valid[p] ? wg : 0.f;
+                    }
                     cur_g = gi;
                 }
 #pragma unroll
@@ -451,11 +514,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
                 }
                 cur_l = li;
             }
-            const float kap = sm.kap[k], ref = sm.ref[k];
             const float2 rv = sm.rowv[k];
 #pragma unroll
             for (int p = 0; p < kP; ++p) {
-                const float ph = fmaf(kap, D[p], ref);
+                const float ph = fmaf(ri.x, D[p], ri.y);
                 const float sn = __builtin_amdgcn_sinf(ph);
                 const float cs = __builtin_amdgcn_cosf(ph);
                 // (cs + j sn)(rv.x + j rv.y)
@@ -568,13 +630,15 @@ struct spgm_plan {
     double *d_kappa = nullptr;
     float2 *d_q = nullptr;
     int *d_status = nullptr;
-    // workspace, sized for ws_B rows
+    // workspace, sized for ws_B rows and ws_splits row ranges
     int ws_B = 0;
     int ws_splits = 0;
-    int4 *d_srt = nullptr;
-    float2 *d_part = nullptr;
-    float2 *d_rs = nullptr;
-    float2 *d_gpart = nullptr;
+    int4 *d_srt = nullptr;       // sorted rows of one minibatch
+    float2 *d_part = nullptr;    // forward partials [tile][row]
+    float2 *d_rs = nullptr;      // scaled residuals, sorted order
+    float2 *d_gpart = nullptr;   // adjoint partials [row range][voxel]
+    int4 *d_srt_all = nullptr;   // sorted rows of a batch of minibatches (solve)
+    size_t srt_all_rows = 0;
     size_t lds_bytes = 0;
     // kernel timing instrumentation
     bool timing = false;
@@ -583,6 +647,8 @@ struct spgm_plan {
 };
 
 namespace {
+
+constexpr size_t kSolveSortRows = size_t(1) << 25;  // rows sorted ahead per solve batch (512 MiB)
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
@@ -619,6 +685,17 @@ int ensure_workspace(spgm_plan *p, int B) {
     return SPGM_OK;
 }
 
+int ensure_sorted_batch(spgm_plan *p, size_t rows) {
+    if (rows <= p->srt_all_rows) return SPGM_OK;
+    hipFree(p->d_srt_all);
+    p->d_srt_all = nullptr;
+    p->srt_all_rows = 0;
+    if (hipMalloc(&p->d_srt_all, sizeof(int4) * rows) != hipSuccess)
+        return fail(SPGM_E_NOMEM, "spgm: sorted-row allocation failed (%zu rows)", rows);
+    p->srt_all_rows = rows;
+    return SPGM_OK;
+}
+
 int launch_check(const char *what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SPGM_E_DEVICE, "spgm: %s launch failed: %s", what, hipGetErrorString(e));
@@ -632,9 +709,13 @@ int check_common(spgm_plan *p, const int32_t *rows, int B) {
     return SPGM_OK;
 }
 
-int run_sort(spgm_plan *p, const int32_t *rows, int B, hipStream_t st) {
+// Sort `count` consecutive minibatches of B rows each (rows[k*B ...]) into srt[k*B ...].
+int run_sort(spgm_plan *p, const int32_t *rows, int B, int count, int4 *srt, hipStream_t st) {
     const int nchunks = (B + kSortChunk - 1) / kSortChunk;
-    k_sort_rows<<<nchunks, kSortThreads, 0, st>>>(p->geo, rows, B, p->d_srt, p->d_status);
+    int p2 = 2;
+    while (p2 < std::min(B, kSortChunk)) p2 <<= 1;
+    k_sort_rows<<<dim3(nchunks, count), kSortThreads, sizeof(unsigned long long) * p2, st>>>(p->geo, rows, B, srt,
+                                                                                           p->d_status);
     return launch_check("sort");
 }
 
@@ -654,39 +735,43 @@ hipEvent_t *timing_slot(spgm_plan *p, std::vector<hipEvent_t> &pool, size_t &use
     return &pool[2 * used++];
 }
 
-int run_forward_partials(spgm_plan *p, const float2 *s, int B, hipStream_t st) {
+int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, hipStream_t st) {
     const int splits = row_splits(p, B);
     const int rpw = (B + splits - 1) / splits;
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
     if (ev) hipEventRecord(ev[0], st);
-    k_fwd_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, p->d_srt, B, rpw, s, p->d_part);
+    k_fwd_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("forward");
 }
 
-int run_adjoint_partials(spgm_plan *p, int B, hipStream_t st) {
+int run_adjoint_partials(spgm_plan *p, const int4 *srt, int B, hipStream_t st) {
     const int splits = row_splits(p, B);
     const int rpw = (B + splits - 1) / splits;
     hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
     if (ev) hipEventRecord(ev[0], st);
-    k_adj_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, p->d_srt, B, rpw, p->d_rs,
-                                                                        p->d_gpart, (int)p->N);
+    k_adj_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs, p->d_gpart,
+                                                                        (int)p->N);
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("adjoint");
 }
 
-int step_impl(spgm_plan *p, const int32_t *rows, int B, const float2 *y, float2 *s, float eta, float alpha,
-              hipStream_t st) {
+int run_row_reduce(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const float2 *y, float2 *out_user,
+                   float2 *out_scaled, hipStream_t st) {
+    k_row_reduce<<<(B + 63) / 64, 64 * kRedGroups, 0, st>>>(p->geo, p->d_part, p->n_tiles, B, srt, rows, y, out_user,
+                                                            out_scaled);
+    return launch_check("row reduce");
+}
+
+// One SPGM iteration on already sorted rows.
+int step_sorted(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const float2 *y, float2 *s, float eta,
+                float alpha, hipStream_t st) {
     int rc;
-    if ((rc = run_sort(p, rows, B, st))) return rc;
-    if ((rc = run_forward_partials(p, s, B, st))) return rc;
-    k_row_reduce<<<(B + 63) / 64, 256, 0, st>>>(p->geo, p->d_part, p->n_tiles, B, p->d_srt, rows, y, nullptr,
-                                                p->d_rs);
-    if ((rc = launch_check("row reduce"))) return rc;
-    if ((rc = run_adjoint_partials(p, B, st))) return rc;
-    const int splits = row_splits(p, B);
-    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, splits, (int)p->N, nullptr, s, eta / (float)B,
-                                                             alpha);
+    if ((rc = run_forward_partials(p, srt, s, B, st))) return rc;
+    if ((rc = run_row_reduce(p, srt, rows, B, y, nullptr, p->d_rs, st))) return rc;
+    if ((rc = run_adjoint_partials(p, srt, B, st))) return rc;
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, row_splits(p, B), (int)p->N, nullptr, s,
+                                                             eta / (float)B, alpha);
     return launch_check("column reduce");
 }
 
@@ -811,12 +896,14 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     g.kappa = p->d_kappa;
     g.q = p->d_q;
     const size_t A = (size_t)(T + R);
-    p->lds_bytes = (sizeof(double) + sizeof(float4)) * A + kSub * (sizeof(float) * 3 + sizeof(float2)) +
+    p->lds_bytes = (sizeof(double) + sizeof(float4)) * A + 16 + kSub * (sizeof(float4) + sizeof(float2)) +
                    std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * 4);
     if (p->lds_bytes > 160 * 1024) {
         spgm_plan_destroy(p);
         return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: LDS footprint exceeds 160 KiB");
     }
+    hipFuncSetAttribute((const void *)k_sort_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(sizeof(unsigned long long) * kSortChunk));
     hipFuncSetAttribute((const void *)k_fwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
     hipFuncSetAttribute((const void *)k_adj_tile, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
     hipGetLastError();
@@ -836,6 +923,7 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_part);
     hipFree(p->d_rs);
     hipFree(p->d_gpart);
+    hipFree(p->d_srt_all);
     for (hipEvent_t e : p->ev_fwd) hipEventDestroy(e);
     for (hipEvent_t e : p->ev_adj) hipEventDestroy(e);
     delete p;
@@ -856,11 +944,9 @@ int spgm_forward(spgm_plan *p, const int32_t *rows, int32_t B, const void *s, vo
     DeviceGuard guard(p->device);
     if ((rc = ensure_workspace(p, B))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = run_sort(p, rows, B, st))) return rc;
-    if ((rc = run_forward_partials(p, (const float2 *)s, B, st))) return rc;
-    k_row_reduce<<<(B + 63) / 64, 256, 0, st>>>(p->geo, p->d_part, p->n_tiles, B, p->d_srt, rows, nullptr,
-                                                (float2 *)y, nullptr);
-    if ((rc = launch_check("row reduce"))) return rc;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    if ((rc = run_forward_partials(p, p->d_srt, (const float2 *)s, B, st))) return rc;
+    if ((rc = run_row_reduce(p, p->d_srt, rows, B, nullptr, (float2 *)y, nullptr, st))) return rc;
     return ok();
 }
 
@@ -871,10 +957,10 @@ int spgm_adjoint(spgm_plan *p, const int32_t *rows, int32_t B, const void *r, vo
     DeviceGuard guard(p->device);
     if ((rc = ensure_workspace(p, B))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = run_sort(p, rows, B, st))) return rc;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
     k_gather_scale<<<(B + 255) / 256, 256, 0, st>>>(p->geo, p->d_srt, B, (const float2 *)r, p->d_rs);
     if ((rc = launch_check("gather"))) return rc;
-    if ((rc = run_adjoint_partials(p, B, st))) return rc;
+    if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
     k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, row_splits(p, B), (int)p->N, (float2 *)g,
                                                              nullptr, 0.f, 0.f);
     if ((rc = launch_check("column reduce"))) return rc;
@@ -895,7 +981,9 @@ int spgm_step(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, void 
     if ((rc = check_step_args(y, s, eta, alpha))) return rc;
     DeviceGuard guard(p->device);
     if ((rc = ensure_workspace(p, B))) return rc;
-    if ((rc = step_impl(p, rows, B, (const float2 *)y, (float2 *)s, eta, alpha, (hipStream_t)stream))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    if ((rc = step_sorted(p, p->d_srt, rows, B, (const float2 *)y, (float2 *)s, eta, alpha, st))) return rc;
     return ok();
 }
 
@@ -907,10 +995,21 @@ int spgm_solve(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, cons
     if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve: iters must be >= 0");
     DeviceGuard guard(p->device);
     if ((rc = ensure_workspace(p, B))) return rc;
-    for (int k = 0; k < iters; ++k) {
-        if ((rc = step_impl(p, rows + (size_t)k * B, B, (const float2 *)y, (float2 *)s, eta, alpha,
-                            (hipStream_t)stream)))
-            return rc;
+    if (iters == 0) return ok();
+    hipStream_t st = (hipStream_t)stream;
+    // The minibatch table is an input, so all of its minibatches are sorted ahead in one launch
+    // per batch of iterations; the iterations then run back to back on the sorted tables.
+    const int per = (int)std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
+    if ((rc = ensure_sorted_batch(p, (size_t)per * B))) return rc;
+    for (int k0 = 0; k0 < iters; k0 += per) {
+        const int cnt = std::min(per, iters - k0);
+        const int32_t *rk = rows + (size_t)k0 * B;
+        if ((rc = run_sort(p, rk, B, cnt, p->d_srt_all, st))) return rc;
+        for (int k = 0; k < cnt; ++k) {
+            if ((rc = step_sorted(p, p->d_srt_all + (size_t)k * B, rk + (size_t)k * B, B, (const float2 *)y,
+                                  (float2 *)s, eta, alpha, st)))
+                return rc;
+        }
     }
     return ok();
 }
