@@ -16,8 +16,10 @@
 //                    and complex soft threshold (the prox of the l1 norm in Eq. 5).
 // Every reduction runs in a fixed order, so results are bitwise reproducible run to run.
 //
-// Geometry per tile.  The grid is cut into 8 x 8 x 4 voxel bricks (one brick per work-group of
-// 256 lanes; each lane owns one (x, y) column of 4 voxels).  The two antenna arrays are called
+// Geometry per tile.  The grid is cut into 8 x 8 x 4 voxel bricks, one brick per work-group.
+// Each of the work-group's eight waves covers the whole brick (a lane owns one (x, y) column
+// of 4 voxels) and takes its own share of the rows, so the brick's LDS tables are shared by
+// eight waves.  The two antenna arrays are called
 // G (the sort-major side, whose per-voxel distance terms live in registers and are rebuilt when
 // the G antenna changes) and L (the other side, whose per-voxel terms are staged in LDS for
 // every L antenna).  L is the smaller array.
@@ -46,11 +48,12 @@
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kThreads = 256;                 // 4 waves per work-group
+constexpr int kWaves = 8;                     // waves per work-group, all on the same brick
+constexpr int kThreads = kWaves * 64;
 constexpr int kBX = 8, kBY = 8, kBZ = 4;      // voxel brick
 constexpr int kBrick = kBX * kBY * kBZ;       // 256 voxels, one (x, y) column per lane
 constexpr int kP = kBZ;                       // voxels per lane
-constexpr int kSub = 256;                     // rows staged in LDS at a time (64 per wave)
+constexpr int kSub = kThreads;                // rows staged in LDS at a time (64 per wave)
 constexpr int kMaxL = 64;                     // largest L array (LDS: kMaxL * 256 * 8 B)
 constexpr int kMaxAnt = 512;                  // T + R
 constexpr int kSortChunk = 16384;             // rows sorted by one work-group
@@ -248,12 +251,12 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int
         sm.antg[a] = make_float4((float)gx, (float)gy, (float)gz, (float)d);
     }
     __syncthreads();
-    const int v = threadIdx.x;  // brick voxel: lane -> (x, y), wave -> z
+    const int v = threadIdx.x % kBrick;  // brick voxel: lane -> (x, y), (wave mod 4) -> z
     const int lx = (v & 63) & 7, ly = (v & 63) >> 3, lz = v >> 6;
     const bool inside = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + lz < g.nz;
     float ex, ey, ez;
     local_offset(g, lx, ly, lz, ex, ey, ez);
-    for (int li = 0; li < g.nL; ++li) {
+    for (int li = threadIdx.x / kBrick; li < g.nL; li += kThreads / kBrick) {
         float dl = 0.f, wl = 0.f;
         if (inside) comp_offset(ex, ey, ez, sm.antg[ant_of_l(g, li)], dl, wl);
         sm.lside[li * kBrick + v] = make_float2(dl, wl);  // voxels outside the grid contribute 0
@@ -533,17 +536,17 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
         gr[p] = fmaf(W[p], hr[p], gr[p]);
         gi_[p] = fmaf(W[p], hi[p], gi_[p]);
     }
-    // Combine the four waves in a fixed order.
+    // Combine the waves in a fixed order.
     __syncthreads();
-    float2 *red = sm.lside;  // 4 x 256 float2, the L-side terms are no longer needed
+    float2 *red = sm.lside;  // kWaves x 256 float2, the L-side terms are no longer needed
 #pragma unroll
     for (int p = 0; p < kP; ++p) red[wave * kBrick + p * kWave + lane] = make_float2(gr[p], gi_[p]);
     __syncthreads();
     const int v = threadIdx.x;
     const int ix = bx * kBX + ((v & 63) & 7), iy = by * kBY + ((v & 63) >> 3), iz = bz * kBZ + (v >> 6);
-    if (ix < g.nx && iy < g.ny && iz < g.nz) {
+    if (v < kBrick && ix < g.nx && iy < g.ny && iz < g.nz) {
         float2 acc = red[v];
-        for (int w = 1; w < 4; ++w) {
+        for (int w = 1; w < kWaves; ++w) {
             acc.x += red[w * kBrick + v].x;
             acc.y += red[w * kBrick + v].y;
         }
@@ -897,7 +900,7 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     g.q = p->d_q;
     const size_t A = (size_t)(T + R);
     p->lds_bytes = (sizeof(double) + sizeof(float4)) * A + 16 + kSub * (sizeof(float4) + sizeof(float2)) +
-                   std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * 4);
+                   std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * kWaves);
     if (p->lds_bytes > 160 * 1024) {
         spgm_plan_destroy(p);
         return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: LDS footprint exceeds 160 KiB");
