@@ -63,8 +63,11 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4"])
-    ap.add_argument("--cpu-iters", type=int, default=2, help="iterations of the oracle timed on the host")
+    ap.add_argument("--cpu-iters", type=int, default=5, help="iterations of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first launch one plain copy-like kernel (torch.neg) that reads and writes this many "
+                         "bytes, as a known-size reference for the HBM byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -79,6 +82,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_bytes > 0:
+        a = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log("copy reference: %d bytes read, %d bytes written" % (a.numel() * 4, b.numel() * 4))
+        del a, b
     wl = args.workload
     cfg = W.CONFIGS[wl]
     geom = W.config_geometry(wl)
