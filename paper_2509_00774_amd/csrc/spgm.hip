@@ -144,6 +144,23 @@ __device__ __forceinline__ void comp_offset(float ex, float ey, float ez, float4
     w = 1.0f / d;
 }
 
+// Same quantities with hardware reciprocal square root / reciprocal, each refined by one Newton
+// step (relative error about 1e-7, like the correctly rounded forms, at a third of the cost).
+__device__ __forceinline__ void comp_offset_fast(float ex, float ey, float ez, float ee, float4 ga, float &delta,
+                                                 float &w) {
+    const float vx = ex + ga.x, vy = ey + ga.y, vz = ez + ga.z;
+    const float d2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
+    float r = __builtin_amdgcn_rsqf(d2);
+    r = r * fmaf(-0.5f * d2 * r, r, 1.5f);            // Newton step for 1/sqrt(d2)
+    const float d = d2 * r;
+    const float den = d + ga.w;
+    float inv = __builtin_amdgcn_rcpf(den);
+    inv = inv * fmaf(-den, inv, 2.0f);                // Newton step for 1/den
+    const float num = fmaf(2.0f, fmaf(ex, ga.x, fmaf(ey, ga.y, ez * ga.z)), ee);
+    delta = num * inv;
+    w = r;
+}
+
 // Decode measurement index m = (f*T + t)*R + r into (f, G index, L index).
 __device__ __forceinline__ void decode_row(const Geo &g, int m, int &f, int &gi, int &li) {
     const int r = m % g.R;
@@ -219,12 +236,19 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_rows(Geo g, const int32_t
 // L-side per-voxel terms, staged in LDS.
 // ------------------------------------------------------------------------------------------
 struct TileSmem {
-    float4 *antg;   // [T+R]: (c - r_a) float32, |c - r_a| float32
-    double *antd;   // [T+R]: |c - r_a| float64
-    float2 *lside;  // [nL][256]: (delta, w) per L antenna per brick voxel
-    float4 *rowinfo; // [kSub]: (kappa, reference phase, G index | L index << 16 as bits, 0)
+    float4 *antg;    // [T+R]: (c - r_a) float32, |c - r_a| float32
+    double *antd;    // [T+R]: |c - r_a| float64
+    float4 *rowinfo; // [kSub]: (kappa, reference phase, packed row word as bits, 0)
     float2 *rowv;    // [kSub]: forward row sums / adjoint scaled residuals
+    float2 *lside;   // [nL][256]: (delta, w) per L antenna per brick voxel
 };
+
+// Packed row word: G index (bits 0-11), L index (bits 12-23), and two flags telling whether the
+// row starts a new G antenna or a new (G, L) pair relative to the previous row of the same wave.
+constexpr int kNewG = 1 << 30;
+constexpr int kNewPair = 1 << 29;
+__device__ __forceinline__ int row_g(int w) { return w & 0xfff; }
+__device__ __forceinline__ int row_l(int w) { return (w >> 12) & 0xfff; }
 
 __device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
     TileSmem t;
@@ -256,25 +280,47 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int
     const bool inside = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + lz < g.nz;
     float ex, ey, ez;
     local_offset(g, lx, ly, lz, ex, ey, ez);
+    const float ee = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
     for (int li = threadIdx.x / kBrick; li < g.nL; li += kThreads / kBrick) {
         float dl = 0.f, wl = 0.f;
-        if (inside) comp_offset(ex, ey, ez, sm.antg[ant_of_l(g, li)], dl, wl);
+        if (inside) comp_offset_fast(ex, ey, ez, ee, sm.antg[ant_of_l(g, li)], dl, wl);
         sm.lside[li * kBrick + v] = make_float2(dl, wl);  // voxels outside the grid contribute 0
     }
 }
 
-// Stage row data of sorted rows [base, base + nsub): float32 kappa, per-brick reference phase
-// (float64, reduced to [-1/2, 1/2] turn), packed (G, L) indices.
-__device__ __forceinline__ void stage_rows(const Geo &g, const TileSmem &sm, const int4 *__restrict__ srt,
-                                           int base, int nsub) {
-    const int k = threadIdx.x;
-    if (k < nsub) {
-        const int4 info = srt[base + k];
-        const double kap = g.kappa[info.y];
-        double ph = kap * (sm.antd[ant_of_g(g, info.z)] + sm.antd[ant_of_l(g, info.w)]);
-        ph -= rint(ph);
-        sm.rowinfo[k] = make_float4((float)kap, (float)ph, __int_as_float(info.z | (info.w << 16)), 0.f);
+// Each wave owns a contiguous run of the work-group's sorted rows [r0, r1): wave w takes
+// [wb, we), a multiple of 64 rows long, so antenna changes stay as rare as in the sorted order.
+__device__ __forceinline__ void wave_rows(int r0, int r1, int w, int &wb, int &we, int &nsub) {
+    const int per = ((r1 - r0 + kWaves - 1) / kWaves + kWave - 1) / kWave * kWave;
+    wb = min(r1, r0 + w * per);
+    we = min(r1, wb + per);
+    nsub = per / kWave;  // sub-chunks of 64 rows per wave (same for every wave)
+}
+
+// Stage sub-chunk j: thread t holds row wb(t/64) + 64 j + t%64 of its wave's run.  Returns the
+// sorted row index (or -1).  Row data: float32 kappa, the per-brick reference phase (float64,
+// reduced to [-1/2, 1/2] turn), the packed row word.
+__device__ __forceinline__ int stage_rows(const Geo &g, const TileSmem &sm, const int4 *__restrict__ srt, int r0,
+                                          int r1, int j) {
+    const int t = threadIdx.x;
+    int wb, we, nsub;
+    wave_rows(r0, r1, t / kWave, wb, we, nsub);
+    const int r = wb + j * kWave + (t % kWave);
+    if (r >= we) return -1;
+    const int4 info = srt[r];
+    const double kap = g.kappa[info.y];
+    double ph = kap * (sm.antd[ant_of_g(g, info.z)] + sm.antd[ant_of_l(g, info.w)]);
+    ph -= rint(ph);
+    int word = info.z | (info.w << 12);
+    if (r == wb) {
+        word |= kNewG | kNewPair;
+    } else {
+        const int4 prev = srt[r - 1];
+        if (prev.z != info.z) word |= kNewG | kNewPair;
+        else if (prev.w != info.w) word |= kNewPair;
     }
+    sm.rowinfo[t] = make_float4((float)kap, (float)ph, __int_as_float(word), 0.f);
+    return r;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -292,97 +338,105 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
     stage_tile(g, sm, bx, by, bz);
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = uniform(threadIdx.x >> 6);  // wave-uniform: keeps row loops on the scalar unit
     const int lx = lane & 7, ly = lane >> 3;
     const int ix = bx * kBX + lx, iy = by * kBY + ly;
-    float ex[kP], ey[kP], ez[kP], sr[kP], si[kP];
+    float ex[kP], ey[kP], ez[kP], ee[kP], sr[kP], si[kP];
     bool valid[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
         const int iz = bz * kBZ + p;
         valid[p] = ix < g.nx && iy < g.ny && iz < g.nz;
         local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
+        ee[p] = fmaf(ex[p], ex[p], fmaf(ey[p], ey[p], ez[p] * ez[p]));
         float2 sv = make_float2(0.f, 0.f);
         if (valid[p]) sv = s[((size_t)iz * g.ny + iy) * g.nx + ix];
         sr[p] = sv.x;
         si[p] = sv.y;
     }
+    const float2 *lbase = sm.lside + lane;  // + li * kBrick + p * kWave
 
     float dG[kP], usr[kP], usi[kP], D[kP], ur[kP], ui[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) dG[p] = usr[p] = usi[p] = D[p] = ur[p] = ui[p] = 0.f;
-    int cur_g = -1, cur_l = -1;
+    float accr[16], acci[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) accr[q] = acci[q] = 0.f;
     const bool b3 = lane & 8, b2 = lane & 4;
+    int wb, we, nsub;
+    wave_rows(r0, r1, wave, wb, we, nsub);
+    const float4 *rinfo = sm.rowinfo + wave * kWave;
 
-    for (int base = r0; base < r1; base += kSub) {
-        const int nsub = min(kSub, r1 - base);
+    for (int j = 0; j < nsub; ++j) {
         __syncthreads();  // previous sub-chunk fully consumed; L-side staged
-        stage_rows(g, sm, srt, base, nsub);
+        const int my_row = stage_rows(g, sm, srt, r0, r1, j);
         __syncthreads();
-        const int kb = wave * kWave;
-        const int ke = min(nsub, kb + kWave);
+        const int cnt = max(0, min(kWave, we - wb - j * kWave));
         // Blocks of up to 16 rows that share the G antenna; one transposed reduction per block.
-        for (int k0 = kb; k0 < ke;) {
-            const int g0 = uniform(__float_as_int(sm.rowinfo[k0].z)) & 0xffff;
-            if (g0 != cur_g) {
-                const float4 ga = sm.antg[ant_of_g(g, g0)];
+        for (int i0 = 0; i0 < cnt;) {
+            const int w0 = uniform(__float_as_int(rinfo[i0].z));
+            if (w0 & kNewG) {
+                const float4 ga = sm.antg[ant_of_g(g, row_g(w0))];
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
                     float dg, wg;
-                    comp_offset(ex[p], ey[p], ez[p], ga, dg, wg);
+                    comp_offset_fast(ex[p], ey[p], ez[p], ee[p], ga, dg, wg);
                     dG[p] = valid[p] ? dg : 0.f;
                     usr[p] = valid[p] ? wg * sr[p] : 0.f;
                     usi[p] = valid[p] ? wg * si[p] : 0.f;
                 }
-                cur_g = g0;
-                cur_l = -1;
             }
-            // block length: rows k0 .. k0+len-1 all use G antenna g0
+            // block length: rows i0 .. i0+len-1 all use the same G antenna
             const int q = lane & 15;
-            const int kq = k0 + q;
-            const bool other = kq >= ke || ((__float_as_int(sm.rowinfo[min(kq, ke - 1)].z) & 0xffff) != g0);
-            const unsigned long long stop = __ballot(other) & 0xffffull;
-            const int len = stop ? __ffsll((long long)stop) - 1 : 16;
-            float accr[16], acci[16];
+            const int iq = i0 + q;
+            const bool stop = iq >= cnt || (q > 0 && (__float_as_int(rinfo[min(iq, cnt - 1)].z) & kNewG));
+            const unsigned long long stops = __ballot(stop) & 0xffffull;
+            const int len = stops ? __ffsll((long long)stops) - 1 : 16;
 #pragma unroll
             for (int qq = 0; qq < 16; ++qq) {
-                float ar = 0.f, ai = 0.f;
                 if (qq < len) {
-                    const float4 ri = sm.rowinfo[k0 + qq];
-                    const int li = uniform(__float_as_int(ri.z)) >> 16;
-                    if (li != cur_l) {
+                    const float4 ri = rinfo[i0 + qq];
+                    const int word = uniform(__float_as_int(ri.z));
+                    if (word & kNewPair) {
+                        const float2 *lp = lbase + row_l(word) * kBrick;
 #pragma unroll
                         for (int p = 0; p < kP; ++p) {
-                            const float2 lv = sm.lside[li * kBrick + p * kWave + lane];
+                            const float2 lv = lp[p * kWave];
                             D[p] = dG[p] + lv.x;
                             ur[p] = lv.y * usr[p];
                             ui[p] = lv.y * usi[p];
                         }
-                        cur_l = li;
                     }
+                    float ar, ai;
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
                         const float ph = fmaf(ri.x, D[p], ri.y);
                         const float sn = __builtin_amdgcn_sinf(ph);
                         const float cs = __builtin_amdgcn_cosf(ph);
                         // (cs - j sn)(ur + j ui)
-                        ar = fmaf(cs, ur[p], ar);
+                        if (p == 0) {
+                            ar = cs * ur[p];
+                            ai = cs * ui[p];
+                        } else {
+                            ar = fmaf(cs, ur[p], ar);
+                            ai = fmaf(cs, ui[p], ai);
+                        }
                         ar = fmaf(sn, ui[p], ar);
-                        ai = fmaf(cs, ui[p], ai);
                         ai = fmaf(-sn, ur[p], ai);
                     }
+                    accr[qq] = ar;
+                    acci[qq] = ai;
                 }
-                accr[qq] = ar;
-                acci[qq] = ai;
             }
+            // Rows at or beyond len hold stale values; their sums are discarded below.
             const float tr = wave_transpose_sum16(accr, b3, b2);
             const float ti = wave_transpose_sum16(acci, b3, b2);
             const int row = lane >> 2;
-            if ((lane & 3) == 0 && row < len) sm.rowv[k0 + row] = make_float2(tr, ti);
-            k0 += len;
+            if ((lane & 3) == 0 && row < len) sm.rowv[wave * kWave + i0 + row] = make_float2(tr, ti);
+            i0 += len;
         }
         __syncthreads();
-        if ((int)threadIdx.x < nsub) part[(size_t)tile * B + base + threadIdx.x] = sm.rowv[threadIdx.x];
+        if (my_row >= 0) part[(size_t)tile * B + my_row] = sm.rowv[threadIdx.x];
     }
 }
 
@@ -449,7 +503,9 @@ __global__ __launch_bounds__(256) void k_gather_scale(Geo g, const int4 *__restr
 
 // ------------------------------------------------------------------------------------------
 // 4. Adjoint partials: gpart[split][n] = sum over the split's rows of conj(A_{i,n}/q_f) rs_i,
-//    with rs_i = conj(q_f) r_i, one voxel column per lane, rows shared by the four waves.
+//    with rs_i = conj(q_f) r_i, one voxel column per lane, rows shared by the eight waves.
+//    Rows of one (G, L) pair share the amplitude 1/(d_G d_L) of each voxel, so their terms are
+//    summed first and scaled once when the pair ends.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
                                                        const float2 *__restrict__ rs, float2 *__restrict__ gpart,
@@ -464,60 +520,62 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
     stage_tile(g, sm, bx, by, bz);
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = uniform(threadIdx.x >> 6);  // wave-uniform: keeps row loops on the scalar unit
     const int lx = lane & 7, ly = lane >> 3;
-    float ex[kP], ey[kP], ez[kP];
+    float ex[kP], ey[kP], ez[kP], ee[kP];
     bool valid[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
         local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
+        ee[p] = fmaf(ex[p], ex[p], fmaf(ey[p], ey[p], ez[p] * ez[p]));
         valid[p] = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + p < g.nz;
     }
+    const float2 *lbase = sm.lside + lane;
 
     float dG[kP], wG[kP], D[kP], W[kP], hr[kP], hi[kP], gr[kP], gi_[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) dG[p] = wG[p] = D[p] = W[p] = hr[p] = hi[p] = gr[p] = gi_[p] = 0.f;
-    int cur_g = -1, cur_l = -1;
+    int wb, we, nsub;
+    wave_rows(r0, r1, wave, wb, we, nsub);
+    const float4 *rinfo = sm.rowinfo + wave * kWave;
+    const float2 *rvals = sm.rowv + wave * kWave;
 
-    for (int base = r0; base < r1; base += kSub) {
-        const int nsub = min(kSub, r1 - base);
+    for (int j = 0; j < nsub; ++j) {
         __syncthreads();
-        stage_rows(g, sm, srt, base, nsub);
-        if ((int)threadIdx.x < nsub) sm.rowv[threadIdx.x] = rs[base + threadIdx.x];
+        const int my_row = stage_rows(g, sm, srt, r0, r1, j);
+        if (my_row >= 0) sm.rowv[threadIdx.x] = rs[my_row];
         __syncthreads();
-        const int kb = wave * kWave;
-        const int ke = min(nsub, kb + kWave);
-        for (int k = kb; k < ke; ++k) {
-            const float4 ri = sm.rowinfo[k];
-            const int gl = uniform(__float_as_int(ri.z));
-            const int gi = gl & 0xffff, li = gl >> 16;
-            if (gi != cur_g || li != cur_l) {
+        const int cnt = max(0, min(kWave, we - wb - j * kWave));
+        for (int i = 0; i < cnt; ++i) {
+            const float4 ri = rinfo[i];
+            const float2 rv = rvals[i];
+            const int word = uniform(__float_as_int(ri.z));
+            if (word & kNewPair) {
+                // close the previous pair and set up the new one
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
                     gr[p] = fmaf(W[p], hr[p], gr[p]);
                     gi_[p] = fmaf(W[p], hi[p], gi_[p]);
                     hr[p] = hi[p] = 0.f;
                 }
-                if (gi != cur_g) {
-                    const float4 ga = sm.antg[ant_of_g(g, gi)];
+                if (word & kNewG) {
+                    const float4 ga = sm.antg[ant_of_g(g, row_g(word))];
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
                         float dg, wg;
-                        comp_offset(ex[p], ey[p], ez[p], ga, dg, wg);
+                        comp_offset_fast(ex[p], ey[p], ez[p], ee[p], ga, dg, wg);
                         dG[p] = valid[p] ? dg : 0.f;
                         wG[p] = valid[p] ? wg : 0.f;
                     }
-                    cur_g = gi;
                 }
+                const float2 *lp = lbase + row_l(word) * kBrick;
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
-                    const float2 lv = sm.lside[li * kBrick + p * kWave + lane];
+                    const float2 lv = lp[p * kWave];
                     D[p] = dG[p] + lv.x;
                     W[p] = wG[p] * lv.y;
                 }
-                cur_l = li;
             }
-            const float2 rv = sm.rowv[k];
 #pragma unroll
             for (int p = 0; p < kP; ++p) {
                 const float ph = fmaf(ri.x, D[p], ri.y);
