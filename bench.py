@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4"])
     ap.add_argument("--cpu-iters", type=int, default=5, help="iterations of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phase", default="comp32", choices=["comp32", "f64", "naive32"],
+                    help="phase precision variant of the projector")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first launch one plain copy-like kernel (torch.neg) that reads and writes this many "
                          "bytes, as a known-size reference for the HBM byte counters")
@@ -104,7 +106,8 @@ def main():
     rows = W.config_rows(wl, K=max(Wm + K, args.cpu_iters))
     s_true, idx = W.config_scene(wl)
 
-    plan = binding.Plan(geom)
+    phase_mode = {"comp32": binding.PHASE_COMP32, "f64": binding.PHASE_F64, "naive32": binding.PHASE_NAIVE32}[args.phase]
+    plan = binding.Plan(geom, phase_mode=phase_mode)
     # Synthetic measurements: forward projection of the seeded scene by the library itself,
     # plus seeded noise at the workload's SNR.
     all_rows = torch.arange(M, dtype=torch.int32, device=dev)
@@ -146,7 +149,7 @@ def main():
     kname, kavg = ("k_fwd_tile", fwd_avg) if fwd_avg >= adj_avg else ("k_adj_tile", adj_avg)
     achieved = entries * SLOTS_PER_ENTRY / kavg / 1e12
     peak = VALU_SLOTS_PER_S / 1e12
-    traffic = stored_traffic(kname, wl)
+    traffic = stored_traffic(kname, wl) if args.phase == "comp32" else None
     roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
@@ -189,7 +192,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %d Tx + %d Rx, %d frequencies, %dx%dx%d voxels, B=%d rows per minibatch" % (
             wl, cfg["T"], cfg["R"], cfg["F"], *cfg["grid"], B),
-            "M": M, "N": N, "B": B, "phase": "compensated fp32 (fp64 per-tile reference)"},
+            "M": M, "N": N, "B": B, "phase": {"comp32": "compensated fp32 (fp64 per-tile reference)",
+                                              "f64": "fp64 distance and phase", "naive32": "naive fp32"}[args.phase]},
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if rel_vs_oracle is None else float("%.3e" % rel_vs_oracle),
         "rel_l2_vs_oracle_after_iters": n_par,

@@ -236,11 +236,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_rows(Geo g, const int32_t
 // L-side per-voxel terms, staged in LDS.
 // ------------------------------------------------------------------------------------------
 struct TileSmem {
-    float4 *antg;    // [T+R]: (c - r_a) float32, |c - r_a| float32
-    double *antd;    // [T+R]: |c - r_a| float64
-    float4 *rowinfo; // [kSub]: (kappa, reference phase, packed row word as bits, 0)
+    float4 *antg;    // [T+R]: COMP32 (c - r_a, |c - r_a|) / NAIVE32 (r_a, 0), float32
+    double *antd;    // [T+R]: COMP32 |c - r_a| float64
+    double4 *antg64; // [T+R]: F64 (c - r_a, |c - r_a|) float64 (aliases antg/antd)
+    float4 *rowinfo; // [kSub]: (row data x, row data y, packed row word as bits, 0)
     float2 *rowv;    // [kSub]: forward row sums / adjoint scaled residuals
-    float2 *lside;   // [nL][256]: (delta, w) per L antenna per brick voxel
+    void *lside;     // [nL][256]: per L antenna per brick voxel (layout set by the phase policy)
 };
 
 // Packed row word: G index (bits 0-11), L index (bits 12-23), and two flags telling whether the
@@ -250,41 +251,152 @@ constexpr int kNewPair = 1 << 29;
 __device__ __forceinline__ int row_g(int w) { return w & 0xfff; }
 __device__ __forceinline__ int row_l(int w) { return (w >> 12) & 0xfff; }
 
+constexpr size_t kAntBytes = 32;  // LDS bytes per antenna (largest policy)
+
 __device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
     TileSmem t;
     const int A = g.T + g.R;
     t.antg = reinterpret_cast<float4 *>(smem);
     t.antd = reinterpret_cast<double *>(smem + sizeof(float4) * A);
-    char *p = smem + (sizeof(double) + sizeof(float4)) * A;
-    p += (16 - reinterpret_cast<uintptr_t>(p) % 16) % 16;
+    t.antg64 = reinterpret_cast<double4 *>(smem);
+    char *p = smem + kAntBytes * A;
     t.rowinfo = reinterpret_cast<float4 *>(p);
     t.rowv = reinterpret_cast<float2 *>(t.rowinfo + kSub);
     t.lside = t.rowv + kSub;
     return t;
 }
 
-__device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int bx, int by, int bz) {
-    const double ccx = g.cx + (bx * kBX + 0.5 * (kBX - 1) - 0.5 * (g.nx - 1)) * g.px;
-    const double ccy = g.cy + (by * kBY + 0.5 * (kBY - 1) - 0.5 * (g.ny - 1)) * g.py;
-    const double ccz = g.cz + (bz * kBZ + 0.5 * (kBZ - 1) - 0.5 * (g.nz - 1)) * g.pz;
-    const int A = g.T + g.R;
-    for (int a = threadIdx.x; a < A; a += kThreads) {
-        const double gx = ccx - g.ant[3 * a], gy = ccy - g.ant[3 * a + 1], gz = ccz - g.ant[3 * a + 2];
+__device__ __forceinline__ void brick_centre(const Geo &g, int bx, int by, int bz, double &cx, double &cy,
+                                             double &cz) {
+    cx = g.cx + (bx * kBX + 0.5 * (kBX - 1) - 0.5 * (g.nx - 1)) * g.px;
+    cy = g.cy + (by * kBY + 0.5 * (kBY - 1) - 0.5 * (g.ny - 1)) * g.py;
+    cz = g.cz + (bz * kBZ + 0.5 * (kBZ - 1) - 0.5 * (g.nz - 1)) * g.pz;
+}
+
+// ------------------------------------------------------------------------------------------
+// Phase policies.  Each turns the geometry of a (row, voxel) pair into the float32 phase in
+// turns that feeds v_sin_f32 / v_cos_f32, and supplies the amplitude 1/(d_G d_L).
+//   G state: per lane voxel, rebuilt when the G antenna changes (registers);
+//   L entry: per (L antenna, brick voxel), staged once per brick (LDS);
+//   D      : per lane voxel, the pair's distance term (G state + L entry);
+//   row data (x, y): per row, from f/c and the brick's reference distances.
+// ------------------------------------------------------------------------------------------
+template <int MODE> struct Phase;
+
+// Compensated float32 (default): offsets from the brick centre, float64 per-row reference.
+template <> struct Phase<SPGM_PHASE_COMP32> {
+    using D = float;
+    using LE = float2;  // (delta, 1/d)
+    struct Vox { float ex, ey, ez, ee; };
+    static __device__ Vox vox(const Geo &g, int bx, int by, int bz, int lx, int ly, int lz) {
+        Vox v;
+        local_offset(g, lx, ly, lz, v.ex, v.ey, v.ez);
+        v.ee = fmaf(v.ex, v.ex, fmaf(v.ey, v.ey, v.ez * v.ez));
+        return v;
+    }
+    static __device__ void stage_ant(const Geo &g, const TileSmem &sm, int a, double cx, double cy, double cz) {
+        const double gx = cx - g.ant[3 * a], gy = cy - g.ant[3 * a + 1], gz = cz - g.ant[3 * a + 2];
         const double d = sqrt(gx * gx + gy * gy + gz * gz);
         sm.antd[a] = d;
         sm.antg[a] = make_float4((float)gx, (float)gy, (float)gz, (float)d);
     }
+    static __device__ void geom(const TileSmem &sm, int a, const Vox &v, D &d, float &w) {
+        comp_offset_fast(v.ex, v.ey, v.ez, v.ee, sm.antg[a], d, w);
+    }
+    static __device__ LE lentry(D d, float w) { return make_float2(d, w); }
+    static __device__ D pair_d(D dg, LE le) { return dg + le.x; }
+    static __device__ float lw(LE le) { return le.y; }
+    static __device__ float2 row_data(const TileSmem &sm, double kap, int ga, int la) {
+        double ph = kap * (sm.antd[ga] + sm.antd[la]);
+        ph -= rint(ph);
+        return make_float2((float)kap, (float)ph);
+    }
+    static __device__ float phase(float4 ri, D d) { return fmaf(ri.x, d, ri.y); }
+};
+
+// Float64 distances and phase, reduced modulo one turn in float64, then float32 sin/cos.
+template <> struct Phase<SPGM_PHASE_F64> {
+    using D = double;
+    using LE = double;  // d
+    struct Vox { double ex, ey, ez; };
+    static __device__ Vox vox(const Geo &g, int bx, int by, int bz, int lx, int ly, int lz) {
+        Vox v;
+        v.ex = (lx - 0.5 * (kBX - 1)) * g.px;
+        v.ey = (ly - 0.5 * (kBY - 1)) * g.py;
+        v.ez = (lz - 0.5 * (kBZ - 1)) * g.pz;
+        return v;
+    }
+    static __device__ void stage_ant(const Geo &g, const TileSmem &sm, int a, double cx, double cy, double cz) {
+        const double gx = cx - g.ant[3 * a], gy = cy - g.ant[3 * a + 1], gz = cz - g.ant[3 * a + 2];
+        sm.antg64[a] = make_double4(gx, gy, gz, 0.0);
+    }
+    static __device__ void geom(const TileSmem &sm, int a, const Vox &v, D &d, float &w) {
+        const double4 ga = sm.antg64[a];
+        const double x = v.ex + ga.x, y = v.ey + ga.y, z = v.ez + ga.z;
+        d = sqrt(fma(x, x, fma(y, y, z * z)));
+        w = (float)(1.0 / d);
+    }
+    static __device__ LE lentry(D d, float) { return d; }
+    static __device__ D pair_d(D dg, LE le) { return dg + le; }
+    static __device__ float lw(LE le) { return __builtin_amdgcn_rcpf((float)le); }
+    static __device__ float2 row_data(const TileSmem &, double kap, int, int) {
+        return make_float2(__int_as_float(__double2loint(kap)), __int_as_float(__double2hiint(kap)));
+    }
+    static __device__ float phase(float4 ri, D d) {
+        const double kap = __hiloint2double(__float_as_int(ri.y), __float_as_int(ri.x));
+        const double ph = kap * d;
+        return (float)(ph - floor(ph));
+    }
+};
+
+// Uncompensated float32: absolute float32 positions, float32 distance and phase.
+template <> struct Phase<SPGM_PHASE_NAIVE32> {
+    using D = float;
+    using LE = float2;  // (d, 1/d)
+    struct Vox { float x, y, z; };
+    static __device__ Vox vox(const Geo &g, int bx, int by, int bz, int lx, int ly, int lz) {
+        Vox v;
+        v.x = (float)(g.cx + (bx * kBX + lx - 0.5 * (g.nx - 1)) * g.px);
+        v.y = (float)(g.cy + (by * kBY + ly - 0.5 * (g.ny - 1)) * g.py);
+        v.z = (float)(g.cz + (bz * kBZ + lz - 0.5 * (g.nz - 1)) * g.pz);
+        return v;
+    }
+    static __device__ void stage_ant(const Geo &g, const TileSmem &sm, int a, double, double, double) {
+        sm.antg[a] = make_float4((float)g.ant[3 * a], (float)g.ant[3 * a + 1], (float)g.ant[3 * a + 2], 0.f);
+    }
+    static __device__ void geom(const TileSmem &sm, int a, const Vox &v, D &d, float &w) {
+        const float4 ra = sm.antg[a];
+        const float x = v.x - ra.x, y = v.y - ra.y, z = v.z - ra.z;
+        d = sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+        w = 1.0f / d;
+    }
+    static __device__ LE lentry(D d, float w) { return make_float2(d, w); }
+    static __device__ D pair_d(D dg, LE le) { return dg + le.x; }
+    static __device__ float lw(LE le) { return le.y; }
+    static __device__ float2 row_data(const TileSmem &, double kap, int, int) {
+        return make_float2((float)kap, 0.f);
+    }
+    static __device__ float phase(float4 ri, D d) { return __builtin_amdgcn_fractf(ri.x * d); }
+};
+
+template <int MODE>
+__device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int bx, int by, int bz) {
+    using P = Phase<MODE>;
+    double cx, cy, cz;
+    brick_centre(g, bx, by, bz, cx, cy, cz);
+    const int A = g.T + g.R;
+    for (int a = threadIdx.x; a < A; a += kThreads) P::stage_ant(g, sm, a, cx, cy, cz);
     __syncthreads();
     const int v = threadIdx.x % kBrick;  // brick voxel: lane -> (x, y), (wave mod 4) -> z
     const int lx = (v & 63) & 7, ly = (v & 63) >> 3, lz = v >> 6;
     const bool inside = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + lz < g.nz;
-    float ex, ey, ez;
-    local_offset(g, lx, ly, lz, ex, ey, ez);
-    const float ee = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+    const typename P::Vox vx = P::vox(g, bx, by, bz, lx, ly, lz);
+    typename P::LE *lside = static_cast<typename P::LE *>(sm.lside);
     for (int li = threadIdx.x / kBrick; li < g.nL; li += kThreads / kBrick) {
-        float dl = 0.f, wl = 0.f;
-        if (inside) comp_offset_fast(ex, ey, ez, ee, sm.antg[ant_of_l(g, li)], dl, wl);
-        sm.lside[li * kBrick + v] = make_float2(dl, wl);  // voxels outside the grid contribute 0
+        typename P::D dl = 0;
+        float wl = 0.f;
+        if (inside) P::geom(sm, ant_of_l(g, li), vx, dl, wl);
+        lside[li * kBrick + v] = P::lentry(dl, wl);  // voxels outside the grid contribute 0
     }
 }
 
@@ -298,8 +410,9 @@ __device__ __forceinline__ void wave_rows(int r0, int r1, int w, int &wb, int &w
 }
 
 // Stage sub-chunk j: thread t holds row wb(t/64) + 64 j + t%64 of its wave's run.  Returns the
-// sorted row index (or -1).  Row data: float32 kappa, the per-brick reference phase (float64,
-// reduced to [-1/2, 1/2] turn), the packed row word.
+// sorted row index (or -1).  Row data: the policy's two words (f/c and the per-brick reference
+// phase for COMP32) and the packed row word.
+template <int MODE>
 __device__ __forceinline__ int stage_rows(const Geo &g, const TileSmem &sm, const int4 *__restrict__ srt, int r0,
                                           int r1, int j) {
     const int t = threadIdx.x;
@@ -308,9 +421,7 @@ __device__ __forceinline__ int stage_rows(const Geo &g, const TileSmem &sm, cons
     const int r = wb + j * kWave + (t % kWave);
     if (r >= we) return -1;
     const int4 info = srt[r];
-    const double kap = g.kappa[info.y];
-    double ph = kap * (sm.antd[ant_of_g(g, info.z)] + sm.antd[ant_of_l(g, info.w)]);
-    ph -= rint(ph);
+    const float2 rd = Phase<MODE>::row_data(sm, g.kappa[info.y], ant_of_g(g, info.z), ant_of_l(g, info.w));
     int word = info.z | (info.w << 12);
     if (r == wb) {
         word |= kNewG | kNewPair;
@@ -319,15 +430,18 @@ __device__ __forceinline__ int stage_rows(const Geo &g, const TileSmem &sm, cons
         if (prev.z != info.z) word |= kNewG | kNewPair;
         else if (prev.w != info.w) word |= kNewPair;
     }
-    sm.rowinfo[t] = make_float4((float)kap, (float)ph, __int_as_float(word), 0.f);
+    sm.rowinfo[t] = make_float4(rd.x, rd.y, __int_as_float(word), 0.f);
     return r;
 }
 
 // ------------------------------------------------------------------------------------------
 // 2. Forward partials: part[tile][i] = sum over brick voxels of (A_{row i, n} / q_f) s_n.
 // ------------------------------------------------------------------------------------------
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
                                                        const float2 *__restrict__ s, float2 *__restrict__ part) {
+    using P = Phase<MODE>;
+    using DT = typename P::D;
     extern __shared__ __align__(16) char smem[];
     const TileSmem sm = carve(smem, g);
     const int tile = blockIdx.x;
@@ -335,30 +449,34 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
     const int r1 = min(B, r0 + rows_per_wg);
     int bx, by, bz;
     brick_of(g, tile, bx, by, bz);
-    stage_tile(g, sm, bx, by, bz);
+    stage_tile<MODE>(g, sm, bx, by, bz);
 
     const int lane = threadIdx.x & 63;
     const int wave = uniform(threadIdx.x >> 6);  // wave-uniform: keeps row loops on the scalar unit
     const int lx = lane & 7, ly = lane >> 3;
     const int ix = bx * kBX + lx, iy = by * kBY + ly;
-    float ex[kP], ey[kP], ez[kP], ee[kP], sr[kP], si[kP];
+    typename P::Vox vox[kP];
+    float sr[kP], si[kP];
     bool valid[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
         const int iz = bz * kBZ + p;
         valid[p] = ix < g.nx && iy < g.ny && iz < g.nz;
-        local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
-        ee[p] = fmaf(ex[p], ex[p], fmaf(ey[p], ey[p], ez[p] * ez[p]));
+        vox[p] = P::vox(g, bx, by, bz, lx, ly, p);
         float2 sv = make_float2(0.f, 0.f);
         if (valid[p]) sv = s[((size_t)iz * g.ny + iy) * g.nx + ix];
         sr[p] = sv.x;
         si[p] = sv.y;
     }
-    const float2 *lbase = sm.lside + lane;  // + li * kBrick + p * kWave
+    const typename P::LE *lbase = static_cast<const typename P::LE *>(sm.lside) + lane;  // + li * kBrick + p * kWave
 
-    float dG[kP], usr[kP], usi[kP], D[kP], ur[kP], ui[kP];
+    DT dG[kP], D[kP];
+    float usr[kP], usi[kP], ur[kP], ui[kP];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) dG[p] = usr[p] = usi[p] = D[p] = ur[p] = ui[p] = 0.f;
+    for (int p = 0; p < kP; ++p) {
+        dG[p] = D[p] = 0;
+        usr[p] = usi[p] = ur[p] = ui[p] = 0.f;
+    }
     float accr[16], acci[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) accr[q] = acci[q] = 0.f;
@@ -369,19 +487,20 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
 
     for (int j = 0; j < nsub; ++j) {
         __syncthreads();  // previous sub-chunk fully consumed; L-side staged
-        const int my_row = stage_rows(g, sm, srt, r0, r1, j);
+        const int my_row = stage_rows<MODE>(g, sm, srt, r0, r1, j);
         __syncthreads();
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         // Blocks of up to 16 rows that share the G antenna; one transposed reduction per block.
         for (int i0 = 0; i0 < cnt;) {
             const int w0 = uniform(__float_as_int(rinfo[i0].z));
             if (w0 & kNewG) {
-                const float4 ga = sm.antg[ant_of_g(g, row_g(w0))];
+                const int ga = ant_of_g(g, row_g(w0));
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
-                    float dg, wg;
-                    comp_offset_fast(ex[p], ey[p], ez[p], ee[p], ga, dg, wg);
-                    dG[p] = valid[p] ? dg : 0.f;
+                    DT dg;
+                    float wg;
+                    P::geom(sm, ga, vox[p], dg, wg);
+                    dG[p] = valid[p] ? dg : DT(0);
                     usr[p] = valid[p] ? wg * sr[p] : 0.f;
                     usi[p] = valid[p] ? wg * si[p] : 0.f;
                 }
@@ -398,19 +517,20 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
                     const float4 ri = rinfo[i0 + qq];
                     const int word = uniform(__float_as_int(ri.z));
                     if (word & kNewPair) {
-                        const float2 *lp = lbase + row_l(word) * kBrick;
+                        const typename P::LE *lp = lbase + row_l(word) * kBrick;
 #pragma unroll
                         for (int p = 0; p < kP; ++p) {
-                            const float2 lv = lp[p * kWave];
-                            D[p] = dG[p] + lv.x;
-                            ur[p] = lv.y * usr[p];
-                            ui[p] = lv.y * usi[p];
+                            const typename P::LE lv = lp[p * kWave];
+                            const float wl = P::lw(lv);
+                            D[p] = P::pair_d(dG[p], lv);
+                            ur[p] = wl * usr[p];
+                            ui[p] = wl * usi[p];
                         }
                     }
                     float ar, ai;
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
-                        const float ph = fmaf(ri.x, D[p], ri.y);
+                        const float ph = P::phase(ri, D[p]);
                         const float sn = __builtin_amdgcn_sinf(ph);
                         const float cs = __builtin_amdgcn_cosf(ph);
                         // (cs - j sn)(ur + j ui)
@@ -507,9 +627,12 @@ __global__ __launch_bounds__(256) void k_gather_scale(Geo g, const int4 *__restr
 //    Rows of one (G, L) pair share the amplitude 1/(d_G d_L) of each voxel, so their terms are
 //    summed first and scaled once when the pair ends.
 // ------------------------------------------------------------------------------------------
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
                                                        const float2 *__restrict__ rs, float2 *__restrict__ gpart,
                                                        int N) {
+    using P = Phase<MODE>;
+    using DT = typename P::D;
     extern __shared__ __align__(16) char smem[];
     const TileSmem sm = carve(smem, g);
     const int tile = blockIdx.x;
@@ -517,24 +640,27 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
     const int r1 = min(B, r0 + rows_per_wg);
     int bx, by, bz;
     brick_of(g, tile, bx, by, bz);
-    stage_tile(g, sm, bx, by, bz);
+    stage_tile<MODE>(g, sm, bx, by, bz);
 
     const int lane = threadIdx.x & 63;
     const int wave = uniform(threadIdx.x >> 6);  // wave-uniform: keeps row loops on the scalar unit
     const int lx = lane & 7, ly = lane >> 3;
-    float ex[kP], ey[kP], ez[kP], ee[kP];
+    typename P::Vox vox[kP];
     bool valid[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
-        local_offset(g, lx, ly, p, ex[p], ey[p], ez[p]);
-        ee[p] = fmaf(ex[p], ex[p], fmaf(ey[p], ey[p], ez[p] * ez[p]));
+        vox[p] = P::vox(g, bx, by, bz, lx, ly, p);
         valid[p] = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + p < g.nz;
     }
-    const float2 *lbase = sm.lside + lane;
+    const typename P::LE *lbase = static_cast<const typename P::LE *>(sm.lside) + lane;
 
-    float dG[kP], wG[kP], D[kP], W[kP], hr[kP], hi[kP], gr[kP], gi_[kP];
+    DT dG[kP], D[kP];
+    float wG[kP], W[kP], hr[kP], hi[kP], gr[kP], gi_[kP];
 #pragma unroll
-    for (int p = 0; p < kP; ++p) dG[p] = wG[p] = D[p] = W[p] = hr[p] = hi[p] = gr[p] = gi_[p] = 0.f;
+    for (int p = 0; p < kP; ++p) {
+        dG[p] = D[p] = 0;
+        wG[p] = W[p] = hr[p] = hi[p] = gr[p] = gi_[p] = 0.f;
+    }
     int wb, we, nsub;
     wave_rows(r0, r1, wave, wb, we, nsub);
     const float4 *rinfo = sm.rowinfo + wave * kWave;
@@ -542,7 +668,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
 
     for (int j = 0; j < nsub; ++j) {
         __syncthreads();
-        const int my_row = stage_rows(g, sm, srt, r0, r1, j);
+        const int my_row = stage_rows<MODE>(g, sm, srt, r0, r1, j);
         if (my_row >= 0) sm.rowv[threadIdx.x] = rs[my_row];
         __syncthreads();
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
@@ -559,26 +685,27 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
                     hr[p] = hi[p] = 0.f;
                 }
                 if (word & kNewG) {
-                    const float4 ga = sm.antg[ant_of_g(g, row_g(word))];
+                    const int ga = ant_of_g(g, row_g(word));
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
-                        float dg, wg;
-                        comp_offset_fast(ex[p], ey[p], ez[p], ee[p], ga, dg, wg);
-                        dG[p] = valid[p] ? dg : 0.f;
+                        DT dg;
+                        float wg;
+                        P::geom(sm, ga, vox[p], dg, wg);
+                        dG[p] = valid[p] ? dg : DT(0);
                         wG[p] = valid[p] ? wg : 0.f;
                     }
                 }
-                const float2 *lp = lbase + row_l(word) * kBrick;
+                const typename P::LE *lp = lbase + row_l(word) * kBrick;
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
-                    const float2 lv = lp[p * kWave];
-                    D[p] = dG[p] + lv.x;
-                    W[p] = wG[p] * lv.y;
+                    const typename P::LE lv = lp[p * kWave];
+                    D[p] = P::pair_d(dG[p], lv);
+                    W[p] = wG[p] * P::lw(lv);
                 }
             }
 #pragma unroll
             for (int p = 0; p < kP; ++p) {
-                const float ph = fmaf(ri.x, D[p], ri.y);
+                const float ph = P::phase(ri, D[p]);
                 const float sn = __builtin_amdgcn_sinf(ph);
                 const float cs = __builtin_amdgcn_cosf(ph);
                 // (cs + j sn)(rv.x + j rv.y)
@@ -596,7 +723,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
     }
     // Combine the waves in a fixed order.
     __syncthreads();
-    float2 *red = sm.lside;  // kWaves x 256 float2, the L-side terms are no longer needed
+    float2 *red = static_cast<float2 *>(sm.lside);  // kWaves x 256 float2, L-side terms no longer needed
 #pragma unroll
     for (int p = 0; p < kP; ++p) red[wave * kBrick + p * kWave + lane] = make_float2(gr[p], gi_[p]);
     __syncthreads();
@@ -801,7 +928,17 @@ int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, 
     const int rpw = (B + splits - 1) / splits;
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
     if (ev) hipEventRecord(ev[0], st);
-    k_fwd_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
+    const dim3 grid(p->n_tiles, splits);
+    switch (p->phase_mode) {
+    case SPGM_PHASE_F64:
+        k_fwd_tile<SPGM_PHASE_F64><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
+        break;
+    case SPGM_PHASE_NAIVE32:
+        k_fwd_tile<SPGM_PHASE_NAIVE32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
+        break;
+    default:
+        k_fwd_tile<SPGM_PHASE_COMP32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
+    }
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("forward");
 }
@@ -811,8 +948,20 @@ int run_adjoint_partials(spgm_plan *p, const int4 *srt, int B, hipStream_t st) {
     const int rpw = (B + splits - 1) / splits;
     hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
     if (ev) hipEventRecord(ev[0], st);
-    k_adj_tile<<<dim3(p->n_tiles, splits), kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs, p->d_gpart,
-                                                                        (int)p->N);
+    const dim3 grid(p->n_tiles, splits);
+    switch (p->phase_mode) {
+    case SPGM_PHASE_F64:
+        k_adj_tile<SPGM_PHASE_F64><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs, p->d_gpart,
+                                                                         (int)p->N);
+        break;
+    case SPGM_PHASE_NAIVE32:
+        k_adj_tile<SPGM_PHASE_NAIVE32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs,
+                                                                             p->d_gpart, (int)p->N);
+        break;
+    default:
+        k_adj_tile<SPGM_PHASE_COMP32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs, p->d_gpart,
+                                                                            (int)p->N);
+    }
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("adjoint");
 }
@@ -852,8 +1001,6 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
         return fail(SPGM_E_INVALID, "spgm_plan_create: tx_xyz, rx_xyz and freq_hz must be non-NULL");
     if (phase_mode != SPGM_PHASE_COMP32 && phase_mode != SPGM_PHASE_F64 && phase_mode != SPGM_PHASE_NAIVE32)
         return fail(SPGM_E_INVALID, "spgm_plan_create: unknown phase mode %d", phase_mode);
-    if (phase_mode != SPGM_PHASE_COMP32)
-        return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: phase mode %d is not built yet", phase_mode);
     const int64_t T = gm->n_tx, R = gm->n_rx, F = gm->n_freq;
     const int64_t M = F * T * R;
     const int64_t N = (int64_t)gm->nx * gm->ny * gm->nz;
@@ -957,7 +1104,7 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     g.kappa = p->d_kappa;
     g.q = p->d_q;
     const size_t A = (size_t)(T + R);
-    p->lds_bytes = (sizeof(double) + sizeof(float4)) * A + 16 + kSub * (sizeof(float4) + sizeof(float2)) +
+    p->lds_bytes = kAntBytes * A + kSub * (sizeof(float4) + sizeof(float2)) +
                    std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * kWaves);
     if (p->lds_bytes > 160 * 1024) {
         spgm_plan_destroy(p);
@@ -965,8 +1112,12 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     }
     hipFuncSetAttribute((const void *)k_sort_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(sizeof(unsigned long long) * kSortChunk));
-    hipFuncSetAttribute((const void *)k_fwd_tile, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
-    hipFuncSetAttribute((const void *)k_adj_tile, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
+    const void *tile_kernels[] = {
+        (const void *)k_fwd_tile<SPGM_PHASE_COMP32>, (const void *)k_fwd_tile<SPGM_PHASE_F64>,
+        (const void *)k_fwd_tile<SPGM_PHASE_NAIVE32>, (const void *)k_adj_tile<SPGM_PHASE_COMP32>,
+        (const void *)k_adj_tile<SPGM_PHASE_F64>, (const void *)k_adj_tile<SPGM_PHASE_NAIVE32>};
+    for (const void *k : tile_kernels)
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
     hipGetLastError();
     *out = p;
     return ok();

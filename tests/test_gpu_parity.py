@@ -186,3 +186,59 @@ def test_c1_full_size_sampled(bd):
     vs = np.sort(rng.choice(orc.N, 96, replace=False))
     check(y_gpu[js], orc.forward(rows[js], s.astype(np.complex128)), "c1 forward (24 sampled rows)")
     check(g_gpu[vs], orc.adjoint_voxels(rows, r.astype(np.complex128), vs), "c1 adjoint (96 sampled voxels)")
+
+
+# ---------------------------------------------------------------------------------------
+# Phase-precision variants.  Stated tolerances (relative L2 against the FP64 oracle):
+#   float64 distance and phase   <= 1e-6
+#   compensated float32 (default) <= 1e-5
+#   naive float32                 <= 5e-4 (stated, not a parity claim: the variant exists to
+#                                  show why the compensation is needed)
+# ---------------------------------------------------------------------------------------
+PHASE_TOL = {0: 1e-5, 1: 1e-6, 2: 5e-4}
+PHASE_NAME = {0: "comp32", 1: "f64", 2: "naive32"}
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_phase_modes_c0(bd, mode):
+    geom = W.config_geometry("c0")
+    orc = Oracle(geom)
+    plan = bd.Plan(geom, phase_mode=mode)
+    rows = W.config_rows("c0", K=1)[0]
+    s = W.random_complex(orc.N, seed=31).astype(np.complex64)
+    r = W.random_complex(rows.size, seed=32).astype(np.complex64)
+    y = host(plan.forward(idev(rows), cdev(s)))
+    g = host(plan.adjoint(idev(rows), cdev(r)))
+    ef = rel_l2(y, orc.forward(rows, s.astype(np.complex128)))
+    ea = rel_l2(g, orc.adjoint(rows, r.astype(np.complex128)))
+    say("c0 phase %s: forward %.3e adjoint %.3e (tol %.0e)" % (PHASE_NAME[mode], ef, ea, PHASE_TOL[mode]))
+    assert ef <= PHASE_TOL[mode] and ea <= PHASE_TOL[mode]
+
+
+def test_c2_precision_study(bd):
+    """Large matrix-free case (48 + 48 antennas, 100 f, 128x128x64 voxels, B = 16384): the three
+    variants at full size against the oracle on a seeded 1 % row subsample (forward) and a seeded
+    1 % voxel subsample (adjoint)."""
+    geom = W.config_geometry("c2")
+    orc = Oracle(geom)
+    rows = W.config_rows("c2", K=1)[0]
+    s_scene, _ = W.config_scene("c2")
+    s = s_scene.astype(np.complex64)
+    r = W.random_complex(rows.size, seed=41).astype(np.complex64)
+    rng = np.random.default_rng(42)
+    js = np.sort(rng.choice(rows.size, rows.size // 100, replace=False))
+    vs = np.sort(rng.choice(orc.N, orc.N // 100, replace=False))
+    say("c2: oracle on %d rows x %d voxels and %d voxels x %d rows" % (js.size, orc.N, vs.size, rows.size))
+    y_ref = orc.forward(rows[js], s.astype(np.complex128))
+    g_ref = orc.adjoint_voxels(rows, r.astype(np.complex128), vs)
+    errs = {}
+    for mode in (1, 0, 2):
+        plan = bd.Plan(geom, phase_mode=mode)
+        y = host(plan.forward(idev(rows), cdev(s)))[js]
+        g = host(plan.adjoint(idev(rows), cdev(r)))[vs]
+        plan.close()
+        errs[mode] = (rel_l2(y, y_ref), rel_l2(g, g_ref))
+        say("c2 phase %s: forward %.3e adjoint %.3e (tol %.0e)" % (PHASE_NAME[mode], *errs[mode], PHASE_TOL[mode]))
+    for mode, (ef, ea) in errs.items():
+        assert ef <= PHASE_TOL[mode] and ea <= PHASE_TOL[mode], (PHASE_NAME[mode], ef, ea)
+    assert max(errs[1]) < max(errs[0]) < max(errs[2])
