@@ -110,6 +110,22 @@ int spgm_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d
 int spgm_solve(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, const void *y_d,
                void *s_d, float eta, float alpha, void *stream);
 
+/* Backward of one unrolled SPGM iteration (differentiation of Eq. 5 with the gradient of
+ * Eq. 6 with respect to its input iterate, step size and threshold):
+ *     z = s - (eta/B) A_B^H (A_B s - y_B),   s' = S_tau(z)    (S as in spgm_step, tau = alpha).
+ * For a real loss L, complex gradients carry dL/dRe + j dL/dIm (the convention of PyTorch).
+ * Given s (iterate entering the iteration) and sbar_next = dL/ds', writes
+ *     sbar = dL/ds = zbar - (eta/B) A_B^H A_B zbar,
+ *     zbar = (1 - tau/|z|) sbar' + (tau/|z|) u Re(conj(u) sbar')  where |z| > tau (u = z/|z|), else 0,
+ *     *eta_bar = dL/deta = -(1/B) Re <zbar, A_B^H (A_B s - y_B)>,
+ *     *tau_bar = dL/dtau = -sum_{|z| > tau} Re(conj(u) sbar').
+ * y_d: complex64[M]; s_d, sbar_next_d, sbar_d: complex64[N] (sbar_d may alias sbar_next_d);
+ * eta_bar_d, tau_bar_d: device double[1] each (overwritten).  eta > 0, tau >= 0.  The entries
+ * of A_B are recomputed (the iterate s is the only state kept from the forward pass). */
+int spgm_unrolled_vjp_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d,
+                           const void *s_d, float eta, float tau, const void *sbar_next_d,
+                           void *sbar_d, double *eta_bar_d, double *tau_bar_d, void *stream);
+
 /* Device-detected errors of earlier calls (currently SPGM_E_BADROW).  Synchronises the plan's
  * device, writes the sticky status to *status (SPGM_OK if none) and clears it. */
 int spgm_plan_status(spgm_plan *plan, int32_t *status);

@@ -16,6 +16,8 @@ Functions and the passage each one follows:
 * :meth:`Oracle.lambda_max`                              -- smallest lambda with zero minimiser of Eq. 3 with Eq. 4
 * :meth:`Oracle.lipschitz`                               -- power iteration on A_B^H A_B / B (step-size choice)
 * :func:`nmse`, :func:`psnr_magnitude`                   -- error metrics (Sec. V, PSNR over normalised magnitudes)
+* :func:`unrolled_forward`, :func:`unrolled_vjp`         -- K iterations of Eq. 5 with per-iteration step size
+                                                            and threshold, and their chain-rule gradient
 """
 from __future__ import annotations
 
@@ -246,3 +248,56 @@ def psnr_magnitude(x, ref) -> float:
 
 def library_path() -> str:
     return os.path.abspath(ensure_oracle())
+
+
+# ---------------------------------------------------------------------------------------------
+# Unrolled SPGM with per-iteration step size eta_k and threshold tau_k (Eq. 5 with Eq. 6):
+#     z_k = s_k - (eta_k/B) A_k^H (A_k s_k - y_k),   s_{k+1} = S_{tau_k}(z_k).
+# Gradients of a real loss use the convention dL/dRe + j dL/dIm for complex quantities.
+# ---------------------------------------------------------------------------------------------
+def unrolled_forward(orc, rows_table, y, s0, eta, tau):
+    """All iterates [s_0, ..., s_K] in FP64."""
+    rows_table = np.asarray(rows_table)
+    y = _c128(y).reshape(-1)
+    s = _c128(s0).reshape(-1).copy()
+    out = [s.copy()]
+    for k in range(rows_table.shape[0]):
+        rows = rows_table[k]
+        g = orc.adjoint(rows, orc.forward(rows, s) - y[rows])
+        z = s - (float(eta[k]) / rows.size) * g
+        s = prox_l1(z, float(tau[k]))
+        out.append(s.copy())
+    return out
+
+
+def unrolled_vjp(orc, rows_table, y, iterates, eta, tau, sbar):
+    """Chain rule through the unrolled iterations, last to first.
+
+    Prox: where |z| > tau with u = z/|z|, zbar = (1 - tau/|z|) sbar + (tau/|z|) u Re(conj(u) sbar)
+    and dL/dtau = -sum Re(conj(u) sbar); where |z| <= tau the output is 0 and zbar = 0.
+    Linear step: sbar_k = zbar - (eta/B) A^H A zbar and dL/deta = -(1/B) Re <zbar, A^H (A s - y)>.
+    Returns (dL/ds_0, dL/deta, dL/dtau)."""
+    rows_table = np.asarray(rows_table)
+    y = _c128(y).reshape(-1)
+    K = rows_table.shape[0]
+    sbar = _c128(sbar).reshape(-1).copy()
+    eta_bar = np.zeros(K)
+    tau_bar = np.zeros(K)
+    for k in range(K - 1, -1, -1):
+        rows = rows_table[k]
+        B = rows.size
+        s = iterates[k]
+        g = orc.adjoint(rows, orc.forward(rows, s) - y[rows])
+        z = s - (float(eta[k]) / B) * g
+        r = np.abs(z)
+        on = r > float(tau[k])
+        u = np.zeros_like(z)
+        u[on] = z[on] / r[on]
+        re = np.real(np.conj(u) * sbar)
+        c = np.zeros_like(r)
+        c[on] = float(tau[k]) / r[on]
+        zbar = np.where(on, (1.0 - c) * sbar + c * u * re, 0.0)
+        tau_bar[k] = -np.sum(re[on])
+        eta_bar[k] = -np.real(np.vdot(zbar, g)) / B
+        sbar = zbar - (float(eta[k]) / B) * orc.adjoint(rows, orc.forward(rows, zbar))
+    return sbar, eta_bar, tau_bar

@@ -29,7 +29,7 @@ PHASE_NAIVE32 = 2
 
 EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
             "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
-            "spgm_plan_timing_read")
+            "spgm_plan_timing_read", "spgm_unrolled_vjp_step")
 
 _dp = C.POINTER(C.c_double)
 
@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH):
         "spgm_solve": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_plan_status": [vp, C.POINTER(i32)],
         "spgm_plan_timing": [vp, i32],
+        "spgm_unrolled_vjp_step": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
         "spgm_plan_timing_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                   C.POINTER(C.c_int64)],
     }
@@ -206,6 +207,18 @@ class Plan:
                                     _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
                                     float(eta), float(alpha), _stream_ptr(stream)))
         return s
+
+    def spgm_unrolled_vjp_step(self, rows, y, s, eta, tau, sbar_next, sbar, eta_bar, tau_bar, stream=None):
+        """Backward of one unrolled iteration; eta_bar / tau_bar: float64 device tensors of one element."""
+        import torch
+        B = rows.numel()
+        _check(self._lib.spgm_unrolled_vjp_step(
+            self._h, _dev(rows, torch.int32, "rows"), B, _dev(y, torch.complex64, "y", self.M),
+            _dev(s, torch.complex64, "s", self.N), float(eta), float(tau),
+            _dev(sbar_next, torch.complex64, "sbar_next", self.N), _dev(sbar, torch.complex64, "sbar", self.N),
+            _dev(eta_bar, torch.float64, "eta_bar", 1), _dev(tau_bar, torch.float64, "tau_bar", 1),
+            _stream_ptr(stream)))
+        return sbar
 
     def spgm_plan_status(self):
         st = C.c_int32()

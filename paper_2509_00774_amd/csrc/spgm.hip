@@ -772,6 +772,90 @@ __global__ __launch_bounds__(256) void k_col_reduce(const float2 *__restrict__ g
 }
 
 // ------------------------------------------------------------------------------------------
+// 6. Backward of one unrolled SPGM iteration  s' = S_tau(z),  z = s - (eta/B) g,
+//    g = A_B^H (A_B s - y_B).  Gradients use the real-loss convention dL/dRe + j dL/dIm.
+// ------------------------------------------------------------------------------------------
+constexpr int kVjpThreads = 256;
+
+// Prox VJP per voxel and block partial sums of the two parameter gradients:
+//   |z| > tau, u = z/|z|:  zbar = (1 - tau/|z|) sbar + (tau/|z|) u Re(conj(u) sbar),
+//                          dL/dtau += -Re(conj(u) sbar);   |z| <= tau: zbar = 0;
+//   dL/deta += -(1/B) Re(conj(zbar) g).
+__global__ __launch_bounds__(kVjpThreads) void k_prox_vjp(const float2 *__restrict__ s, const float2 *__restrict__ g,
+                                                          const float2 *__restrict__ sbar, int N, float step,
+                                                          float tau, float inv_b, float2 *__restrict__ zbar,
+                                                          double *__restrict__ part) {
+    __shared__ double red[2][kVjpThreads];
+    const int n = blockIdx.x * kVjpThreads + threadIdx.x;
+    double tb = 0.0, eb = 0.0;
+    if (n < N) {
+        const float2 sv = s[n], gv = g[n], sb = sbar[n];
+        const float zx = fmaf(-step, gv.x, sv.x), zy = fmaf(-step, gv.y, sv.y);
+        const float r = sqrtf(fmaf(zx, zx, zy * zy));
+        float2 zb = make_float2(0.f, 0.f);
+        if (r > tau) {
+            const float ux = zx / r, uy = zy / r;
+            const float re = fmaf(ux, sb.x, uy * sb.y);
+            const float c = tau / r;
+            zb.x = fmaf(c * re, ux, (1.0f - c) * sb.x);
+            zb.y = fmaf(c * re, uy, (1.0f - c) * sb.y);
+            tb = -(double)re;
+            eb = -(double)inv_b * (double)fmaf(zb.x, gv.x, zb.y * gv.y);
+        }
+        zbar[n] = zb;
+    }
+    red[0][threadIdx.x] = tb;
+    red[1][threadIdx.x] = eb;
+    __syncthreads();
+    for (int w = kVjpThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = red[1][0];              // eta
+        part[gridDim.x + blockIdx.x] = red[0][0];  // tau
+    }
+}
+
+// out = zbar - step * h
+__global__ __launch_bounds__(256) void k_axpy_out(const float2 *__restrict__ zbar, const float2 *__restrict__ h, int N,
+                                                  float step, float2 *__restrict__ out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) {
+        const float2 z = zbar[n], hv = h[n];
+        out[n] = make_float2(fmaf(-step, hv.x, z.x), fmaf(-step, hv.y, z.y));
+    }
+}
+
+// Fixed-order sum of the block partials: out[0] = eta gradient, out[1] = tau gradient.
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part, int nb,
+                                                      double *__restrict__ eta_bar, double *__restrict__ tau_bar) {
+    __shared__ double red[2][256];
+    double e = 0.0, t = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        e += part[i];
+        t += part[nb + i];
+    }
+    red[0][threadIdx.x] = e;
+    red[1][threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *eta_bar = red[0][0];
+        *tau_bar = red[1][0];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Host side
 // ------------------------------------------------------------------------------------------
 thread_local std::string g_last_error;
@@ -826,6 +910,8 @@ struct spgm_plan {
     float2 *d_rs = nullptr;      // scaled residuals, sorted order
     float2 *d_gpart = nullptr;   // adjoint partials [row range][voxel]
     int4 *d_srt_all = nullptr;   // sorted rows of a batch of minibatches (solve)
+    float2 *d_vjp = nullptr;     // unrolled backward: g, zbar, h (3 x N) and block partials
+    double *d_vjp_part = nullptr;
     size_t srt_all_rows = 0;
     size_t lds_bytes = 0;
     // kernel timing instrumentation
@@ -985,6 +1071,15 @@ int step_sorted(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const
     return launch_check("column reduce");
 }
 
+int ensure_vjp(spgm_plan *p) {
+    if (p->d_vjp) return SPGM_OK;
+    const int nb = (int)((p->N + kVjpThreads - 1) / kVjpThreads);
+    if (hipMalloc(&p->d_vjp, sizeof(float2) * 3 * (size_t)p->N) != hipSuccess ||
+        hipMalloc(&p->d_vjp_part, sizeof(double) * 2 * (size_t)nb) != hipSuccess)
+        return fail(SPGM_E_NOMEM, "spgm: backward workspace allocation failed");
+    return SPGM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1136,6 +1231,8 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_rs);
     hipFree(p->d_gpart);
     hipFree(p->d_srt_all);
+    hipFree(p->d_vjp);
+    hipFree(p->d_vjp_part);
     for (hipEvent_t e : p->ev_fwd) hipEventDestroy(e);
     for (hipEvent_t e : p->ev_adj) hipEventDestroy(e);
     delete p;
@@ -1223,6 +1320,47 @@ int spgm_solve(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, cons
                 return rc;
         }
     }
+    return ok();
+}
+
+int spgm_unrolled_vjp_step(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, const void *s,
+                           float eta, float tau, const void *sbar_next, void *sbar, double *eta_bar,
+                           double *tau_bar, void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if (!y || !s || !sbar_next || !sbar || !eta_bar || !tau_bar)
+        return fail(SPGM_E_INVALID, "spgm_unrolled_vjp_step: NULL pointer argument");
+    if (!(std::isfinite(eta) && eta > 0) || !(std::isfinite(tau) && tau >= 0))
+        return fail(SPGM_E_INVALID, "spgm_unrolled_vjp_step: eta must be > 0 and tau >= 0, finite");
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B)) || (rc = ensure_vjp(p))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int N = (int)p->N;
+    float2 *g = p->d_vjp, *zbar = p->d_vjp + N, *h = p->d_vjp + 2 * (size_t)N;
+    const int splits = row_splits(p, B);
+    const int nb = (N + kVjpThreads - 1) / kVjpThreads;
+    const float step = eta / (float)B;
+    // recompute g = A_B^H (A_B s - y_B) at the iterate entering the iteration
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    if ((rc = run_forward_partials(p, p->d_srt, (const float2 *)s, B, st))) return rc;
+    if ((rc = run_row_reduce(p, p->d_srt, rows, B, (const float2 *)y, nullptr, p->d_rs, st))) return rc;
+    if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
+    k_col_reduce<<<(N + 255) / 256, 256, 0, st>>>(p->d_gpart, splits, N, g, nullptr, 0.f, 0.f);
+    if ((rc = launch_check("column reduce"))) return rc;
+    // prox VJP and parameter-gradient partials
+    k_prox_vjp<<<nb, kVjpThreads, 0, st>>>((const float2 *)s, g, (const float2 *)sbar_next, N, step, tau,
+                                           1.0f / (float)B, zbar, p->d_vjp_part);
+    if ((rc = launch_check("prox vjp"))) return rc;
+    // h = A_B^H A_B zbar
+    if ((rc = run_forward_partials(p, p->d_srt, zbar, B, st))) return rc;
+    if ((rc = run_row_reduce(p, p->d_srt, rows, B, nullptr, nullptr, p->d_rs, st))) return rc;
+    if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
+    k_col_reduce<<<(N + 255) / 256, 256, 0, st>>>(p->d_gpart, splits, N, h, nullptr, 0.f, 0.f);
+    if ((rc = launch_check("column reduce"))) return rc;
+    k_axpy_out<<<(N + 255) / 256, 256, 0, st>>>(zbar, h, N, step, (float2 *)sbar);
+    if ((rc = launch_check("axpy"))) return rc;
+    k_sum_partials<<<1, 256, 0, st>>>(p->d_vjp_part, nb, eta_bar, tau_bar);
+    if ((rc = launch_check("sum partials"))) return rc;
     return ok();
 }
 

@@ -321,3 +321,63 @@ def test_adjoint_voxel_subset_matches_full_adjoint():
     r = W.random_complex(rows.size, seed=93)
     idx = np.array([0, 5, 17, orc.N - 1])
     assert np.array_equal(orc.adjoint_voxels(rows, r, idx), orc.adjoint(rows, r)[idx])
+
+
+# ---------------------------------------------------------------------------------------
+# Unrolled SPGM gradient (differentiation of Eq. 5 with Eq. 6): the chain-rule VJP against
+# central finite differences in FP64 on log-parameters eta_k = eta0 e^{a_k}, tau_k = tau0 e^{b_k}
+# (h = 1e-3, a 0.1 % relative perturbation), on a scene where no |z| lies within 20 h tau of
+# the threshold (so no finite difference crosses the prox's kink).
+# ---------------------------------------------------------------------------------------
+def _unrolled_problem():
+    from oracle import unrolled_forward
+    geom = W.make_geometry(4, 4, 4, (20e9, 30e9), (4, 4, 2), 5e-3, 0.25, 0.2, seed=101)
+    orc = Oracle(geom)
+    s_true, idx = W.random_scene(orc.N, 0.2, seed=102)
+    y = orc.forward(np.arange(orc.M), s_true) + 0.01 * W.random_complex(orc.M, seed=103)
+    K, B = 4, 24
+    rows = W.draw_rows(orc.M, B, K, seed=104)
+    L = max(orc.lipschitz(r, iters=60, seed=k) for k, r in enumerate(rows))
+    eta = np.array([0.8, 0.9, 1.0, 1.1]) / L
+    tau = 0.05 * orc.lambda_max(y) * eta
+    loss = lambda s: float(np.mean(np.abs(s - s_true) ** 2))
+    return orc, rows, y, s_true, eta, tau, loss, unrolled_forward
+
+
+def test_unrolled_vjp_matches_finite_differences():
+    from oracle import unrolled_vjp
+    orc, rows, y, s_true, eta, tau, loss, fwd = _unrolled_problem()
+    s0 = np.zeros(orc.N, complex)
+    it = fwd(orc, rows, y, s0, eta, tau)
+    # kink margin: every |z_k| stays at least 20 h tau_k away from tau_k
+    h = 1e-3
+    for k in range(rows.shape[0]):
+        g = orc.adjoint(rows[k], orc.forward(rows[k], it[k]) - y[rows[k]])
+        z = it[k] - eta[k] / rows.shape[1] * g
+        assert np.min(np.abs(np.abs(z) - tau[k])) > 20 * h * tau[k]
+    sbar = 2.0 * (it[-1] - s_true) / orc.N   # d mean|s - t|^2 / d(Re + j Im)
+    _, eta_bar, tau_bar = unrolled_vjp(orc, rows, y, it, eta, tau, sbar)
+    for k in range(rows.shape[0]):
+        for which, base, bar in (("eta", eta, eta_bar), ("tau", tau, tau_bar)):
+            plus, minus = base.copy(), base.copy()
+            plus[k] *= np.exp(h)
+            minus[k] *= np.exp(-h)
+            e_args = (plus, tau) if which == "eta" else (eta, plus)
+            m_args = (minus, tau) if which == "eta" else (eta, minus)
+            fd = (loss(fwd(orc, rows, y, s0, *e_args)[-1]) - loss(fwd(orc, rows, y, s0, *m_args)[-1])) / (2 * h)
+            an = base[k] * bar[k]   # dL/d log(param) = param * dL/dparam
+            assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-12) + 1e-14, (which, k, fd, an)
+
+
+def test_unrolled_vjp_initial_iterate_matches_finite_differences():
+    from oracle import unrolled_vjp
+    orc, rows, y, s_true, eta, tau, loss, fwd = _unrolled_problem()
+    s0 = 0.3 * W.random_complex(orc.N, seed=105)
+    it = fwd(orc, rows, y, s0, eta, tau)
+    sbar = 2.0 * (it[-1] - s_true) / orc.N
+    s0bar, _, _ = unrolled_vjp(orc, rows, y, it, eta, tau, sbar)
+    h = 1e-6
+    d = W.random_complex(orc.N, seed=106)
+    fd = (loss(fwd(orc, rows, y, s0 + h * d, eta, tau)[-1]) - loss(fwd(orc, rows, y, s0 - h * d, eta, tau)[-1])) / (2 * h)
+    an = float(np.real(np.vdot(s0bar, d)))   # directional derivative Re<grad, d>
+    assert abs(fd - an) <= 1e-6 * abs(an)
