@@ -110,6 +110,15 @@ int spgm_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d
 int spgm_solve(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, const void *y_d,
                void *s_d, float eta, float alpha, void *stream);
 
+/* spgm_solve executed as a HIP graph: the sort and the launches of all `iters` iterations are
+ * captured once (on a stream owned by the plan) and the instantiated graph is replayed on
+ * `stream`.  The graph is kept for the next call and replayed as long as rows_d, iters, B, y_d,
+ * s_d, eta and alpha are the same (the buffers' contents may change between calls, as in
+ * repeated solves on new measurements); any other arguments re-capture it.  The first call
+ * pays the capture and instantiation cost.  Same results as spgm_solve, bit for bit. */
+int spgm_solve_graph(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, const void *y_d,
+                     void *s_d, float eta, float alpha, void *stream);
+
 /* Backward of one unrolled SPGM iteration (differentiation of Eq. 5 with the gradient of
  * Eq. 6 with respect to its input iterate, step size and threshold):
  *     z = s - (eta/B) A_B^H (A_B s - y_B),   s' = S_tau(z)    (S as in spgm_step, tau = alpha).
@@ -134,7 +143,8 @@ int spgm_plan_status(spgm_plan *plan, int32_t *status);
  * kernels (forward tile, adjoint tile) is bracketed by HIP events recorded on the call's
  * stream.  spgm_plan_timing_read synchronises the plan's device, returns the summed kernel
  * durations (milliseconds) and launch counts since the last read, and resets them.  Any
- * output pointer may be NULL. */
+ * output pointer may be NULL.  Launches made through a captured graph (spgm_solve_graph) are
+ * not timed. */
 int spgm_plan_timing(spgm_plan *plan, int32_t enable);
 int spgm_plan_timing_read(spgm_plan *plan, double *fwd_ms, int64_t *fwd_launches, double *adj_ms,
                           int64_t *adj_launches);

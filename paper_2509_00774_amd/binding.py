@@ -29,7 +29,7 @@ PHASE_NAIVE32 = 2
 
 EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
             "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
-            "spgm_plan_timing_read", "spgm_unrolled_vjp_step")
+            "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph")
 
 _dp = C.POINTER(C.c_double)
 
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH):
         "spgm_adjoint": [vp, vp, i32, vp, vp, vp],
         "spgm_step": [vp, vp, i32, vp, vp, f32, f32, vp],
         "spgm_solve": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
+        "spgm_solve_graph": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_plan_status": [vp, C.POINTER(i32)],
         "spgm_plan_timing": [vp, i32],
         "spgm_unrolled_vjp_step": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
@@ -219,6 +220,18 @@ class Plan:
             _dev(eta_bar, torch.float64, "eta_bar", 1), _dev(tau_bar, torch.float64, "tau_bar", 1),
             _stream_ptr(stream)))
         return sbar
+
+    def spgm_solve_graph(self, rows_table, y, s, eta, alpha, stream=None):
+        """spgm_solve replayed from a captured HIP graph (re-captured when arguments change)."""
+        import torch
+        if rows_table.dim() != 2:
+            raise ValueError("rows_table must be 2-D (iters, B)")
+        K, B = rows_table.shape
+        _check(self._lib.spgm_solve_graph(self._h, _dev(rows_table, torch.int32, "rows_table"), int(K), int(B),
+                                          _dev(y, torch.complex64, "y", self.M),
+                                          _dev(s, torch.complex64, "s", self.N), float(eta), float(alpha),
+                                          _stream_ptr(stream)))
+        return s
 
     def spgm_plan_status(self):
         st = C.c_int32()

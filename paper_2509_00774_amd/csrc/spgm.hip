@@ -912,6 +912,17 @@ struct spgm_plan {
     int4 *d_srt_all = nullptr;   // sorted rows of a batch of minibatches (solve)
     float2 *d_vjp = nullptr;     // unrolled backward: g, zbar, h (3 x N) and block partials
     double *d_vjp_part = nullptr;
+    // captured solve (spgm_solve_graph): one executable graph and the arguments it was made for
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    struct {
+        const int32_t *rows;
+        int iters, B;
+        const void *y;
+        void *s;
+        float eta, alpha;
+    } graph_key{};
     size_t srt_all_rows = 0;
     size_t lds_bytes = 0;
     // kernel timing instrumentation
@@ -934,9 +945,18 @@ int row_splits(const spgm_plan *p, int B) {
     return std::min(want, maxs);
 }
 
+// A captured solve graph holds workspace pointers: drop it whenever the workspace moves.
+void drop_graph(spgm_plan *p) {
+    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+}
+
 int ensure_workspace(spgm_plan *p, int B) {
     const int splits = row_splits(p, B);
     if (B <= p->ws_B && splits <= p->ws_splits) return SPGM_OK;
+    drop_graph(p);
     const int nb = std::max(B, p->ws_B);
     const int ns = std::max(splits, p->ws_splits);
     hipFree(p->d_srt);
@@ -961,6 +981,7 @@ int ensure_workspace(spgm_plan *p, int B) {
 
 int ensure_sorted_batch(spgm_plan *p, size_t rows) {
     if (rows <= p->srt_all_rows) return SPGM_OK;
+    drop_graph(p);
     hipFree(p->d_srt_all);
     p->d_srt_all = nullptr;
     p->srt_all_rows = 0;
@@ -1233,6 +1254,8 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_srt_all);
     hipFree(p->d_vjp);
     hipFree(p->d_vjp_part);
+    drop_graph(p);
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     for (hipEvent_t e : p->ev_fwd) hipEventDestroy(e);
     for (hipEvent_t e : p->ev_adj) hipEventDestroy(e);
     delete p;
@@ -1296,30 +1319,94 @@ int spgm_step(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, void 
     return ok();
 }
 
-int spgm_solve(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, const void *y, void *s, float eta,
-               float alpha, void *stream) {
+// Issue the launches of an iters-iteration solve on `st` (workspace already sized).
+static int solve_launches(spgm_plan *p, const int32_t *rows, int iters, int B, const float2 *y, float2 *s, float eta,
+                          float alpha, hipStream_t st) {
     int rc;
-    if ((rc = check_common(p, rows, B))) return rc;
-    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
-    if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve: iters must be >= 0");
-    DeviceGuard guard(p->device);
-    if ((rc = ensure_workspace(p, B))) return rc;
-    if (iters == 0) return ok();
-    hipStream_t st = (hipStream_t)stream;
     // The minibatch table is an input, so all of its minibatches are sorted ahead in one launch
     // per batch of iterations; the iterations then run back to back on the sorted tables.
     const int per = (int)std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
-    if ((rc = ensure_sorted_batch(p, (size_t)per * B))) return rc;
     for (int k0 = 0; k0 < iters; k0 += per) {
         const int cnt = std::min(per, iters - k0);
         const int32_t *rk = rows + (size_t)k0 * B;
         if ((rc = run_sort(p, rk, B, cnt, p->d_srt_all, st))) return rc;
         for (int k = 0; k < cnt; ++k) {
-            if ((rc = step_sorted(p, p->d_srt_all + (size_t)k * B, rk + (size_t)k * B, B, (const float2 *)y,
-                                  (float2 *)s, eta, alpha, st)))
+            if ((rc = step_sorted(p, p->d_srt_all + (size_t)k * B, rk + (size_t)k * B, B, y, s, eta, alpha, st)))
                 return rc;
         }
     }
+    return SPGM_OK;
+}
+
+static int solve_prepare(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, const void *y, void *s,
+                         float eta, float alpha) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve: iters must be >= 0");
+    if ((rc = ensure_workspace(p, B))) return rc;
+    if (iters == 0) return SPGM_OK;
+    const size_t per = std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
+    return ensure_sorted_batch(p, per * B);
+}
+
+int spgm_solve(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, const void *y, void *s, float eta,
+               float alpha, void *stream) {
+    int rc;
+    if (!p) return fail(SPGM_E_INVALID, "spgm: plan is NULL");
+    DeviceGuard guard(p->device);
+    if ((rc = solve_prepare(p, rows, iters, B, y, s, eta, alpha))) return rc;
+    if (iters == 0) return ok();
+    if ((rc = solve_launches(p, rows, iters, B, (const float2 *)y, (float2 *)s, eta, alpha, (hipStream_t)stream)))
+        return rc;
+    return ok();
+}
+
+int spgm_solve_graph(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, const void *y, void *s, float eta,
+                     float alpha, void *stream) {
+    int rc;
+    if (!p) return fail(SPGM_E_INVALID, "spgm: plan is NULL");
+    DeviceGuard guard(p->device);
+    if ((rc = solve_prepare(p, rows, iters, B, y, s, eta, alpha))) return rc;
+    if (iters == 0) return ok();
+    const bool same = p->graph_exec && p->graph_key.rows == rows && p->graph_key.iters == iters &&
+                      p->graph_key.B == B && p->graph_key.y == y && p->graph_key.s == s &&
+                      p->graph_key.eta == eta && p->graph_key.alpha == alpha;
+    if (!same) {
+        drop_graph(p);
+        if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(SPGM_E_DEVICE, "spgm_solve_graph: stream creation failed");
+        const bool timing = p->timing;
+        p->timing = false;  // no event records inside the captured graph
+        if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            p->timing = timing;
+            return fail(SPGM_E_DEVICE, "spgm_solve_graph: capture failed to start");
+        }
+        rc = solve_launches(p, rows, iters, B, (const float2 *)y, (float2 *)s, eta, alpha, p->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        p->timing = timing;
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess || !g) return fail(SPGM_E_DEVICE, "spgm_solve_graph: capture failed: %s", hipGetErrorString(e));
+        p->graph = g;
+        if (hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            p->graph = nullptr;
+            return fail(SPGM_E_DEVICE, "spgm_solve_graph: graph instantiation failed");
+        }
+        p->graph_key.rows = rows;
+        p->graph_key.iters = iters;
+        p->graph_key.B = B;
+        p->graph_key.y = y;
+        p->graph_key.s = s;
+        p->graph_key.eta = eta;
+        p->graph_key.alpha = alpha;
+    }
+    const hipError_t e = hipGraphLaunch(p->graph_exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_solve_graph: launch failed: %s", hipGetErrorString(e));
     return ok();
 }
 
