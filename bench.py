@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4"])
     ap.add_argument("--cpu-iters", type=int, default=5, help="iterations of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the row-split autotuner")
     ap.add_argument("--eager", action="store_true",
                     help="time the solve as individual launches instead of a captured HIP graph")
     ap.add_argument("--phase", default="comp32", choices=["comp32", "f64", "naive32"],
@@ -110,6 +111,9 @@ def main():
 
     phase_mode = {"comp32": binding.PHASE_COMP32, "f64": binding.PHASE_F64, "naive32": binding.PHASE_NAIVE32}[args.phase]
     plan = binding.Plan(geom, phase_mode=phase_mode)
+    splits = None if args.no_tune else plan.spgm_plan_autotune(B)
+    if splits:
+        log("autotuned row splits: forward %d, adjoint %d" % splits)
     # Synthetic measurements: forward projection of the seeded scene by the library itself,
     # plus seeded noise at the workload's SNR.
     all_rows = torch.arange(M, dtype=torch.int32, device=dev)
@@ -212,7 +216,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %d Tx + %d Rx, %d frequencies, %dx%dx%d voxels, B=%d rows per minibatch" % (
             wl, cfg["T"], cfg["R"], cfg["F"], *cfg["grid"], B),
-            "M": M, "N": N, "B": B, "hip_graph": not args.eager, "phase": {"comp32": "compensated fp32 (fp64 per-tile reference)",
+            "M": M, "N": N, "B": B, "hip_graph": not args.eager,
+            "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]}, "phase": {"comp32": "compensated fp32 (fp64 per-tile reference)",
                                               "f64": "fp64 distance and phase", "naive32": "naive fp32"}[args.phase]},
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if rel_vs_oracle is None else float("%.3e" % rel_vs_oracle),

@@ -135,6 +135,18 @@ int spgm_unrolled_vjp_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, co
                            const void *s_d, float eta, float tau, const void *sbar_next_d,
                            void *sbar_d, double *eta_bar_d, double *tau_bar_d, void *stream);
 
+/* Autotuner.  For minibatch size B, times the forward-tile and adjoint-tile kernels over the
+ * candidate row splits (rows of the minibatch per work-group: splits 1, 2, 3, 4, 6, 8, ... up to
+ * ceil(B/64)) on uniform pseudo-random rows, and keeps the fastest split per kernel for every
+ * later call of this plan with this B.  Results are cached in a JSON file (cache_path, else the
+ * environment variable SPGM_TUNE_CACHE, else no file) keyed by GPU architecture, phase mode,
+ * T, R, F, grid and B; a cached key is applied without timing.  Writes the chosen splits to
+ * *fwd_splits / *adj_splits (either may be NULL).  Synchronous; allocates temporary device
+ * memory.  The adjoint's summation order depends on its split, so results may differ from an
+ * untuned plan in the last bits (within the parity tolerance). */
+int spgm_plan_autotune(spgm_plan *plan, int32_t B, const char *cache_path, int32_t *fwd_splits,
+                       int32_t *adj_splits);
+
 /* Device-detected errors of earlier calls (currently SPGM_E_BADROW).  Synchronises the plan's
  * device, writes the sticky status to *status (SPGM_OK if none) and clears it. */
 int spgm_plan_status(spgm_plan *plan, int32_t *status);

@@ -29,7 +29,7 @@ PHASE_NAIVE32 = 2
 
 EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
             "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
-            "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph")
+            "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph", "spgm_plan_autotune")
 
 _dp = C.POINTER(C.c_double)
 
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH):
         "spgm_step": [vp, vp, i32, vp, vp, f32, f32, vp],
         "spgm_solve": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_solve_graph": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
+        "spgm_plan_autotune": [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(i32)],
         "spgm_plan_status": [vp, C.POINTER(i32)],
         "spgm_plan_timing": [vp, i32],
         "spgm_unrolled_vjp_step": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
@@ -233,6 +234,13 @@ class Plan:
                                           _stream_ptr(stream)))
         return s
 
+    def spgm_plan_autotune(self, B, cache_path=None):
+        """Tune the row splits for minibatch size B; returns (forward splits, adjoint splits)."""
+        fs, as_ = C.c_int32(), C.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self._lib.spgm_plan_autotune(self._h, int(B), path, C.byref(fs), C.byref(as_)))
+        return fs.value, as_.value
+
     def spgm_plan_status(self):
         st = C.c_int32()
         _check(self._lib.spgm_plan_status(self._h, C.byref(st)))
@@ -254,3 +262,4 @@ class Plan:
     step = spgm_step
     solve = spgm_solve
     status = spgm_plan_status
+    autotune = spgm_plan_autotune

@@ -40,6 +40,10 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -929,6 +933,8 @@ struct spgm_plan {
     bool timing = false;
     std::vector<hipEvent_t> ev_fwd, ev_adj;  // pairs: [2k] start, [2k+1] stop
     size_t n_fwd = 0, n_adj = 0;
+    // autotuned row splits per minibatch size: B -> (forward, adjoint)
+    std::map<int, std::pair<int, int>> tuned;
 };
 
 namespace {
@@ -937,12 +943,23 @@ constexpr size_t kSolveSortRows = size_t(1) << 25;  // rows sorted ahead per sol
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
-// Row splits for the tile kernels: enough work-groups to cover the chip a few times, at least
-// 64 rows per work-group.
-int row_splits(const spgm_plan *p, int B) {
+// Row splits for the tile kernels: the autotuned value for this B if there is one, else enough
+// work-groups to cover the chip a few times with at least 64 rows per work-group.
+int max_splits(int B) { return std::max(1, (B + 63) / 64); }
+
+int default_splits(const spgm_plan *p, int B) {
     const int want = std::max(1, (4 * 256 + p->n_tiles - 1) / p->n_tiles);
-    const int maxs = std::max(1, (B + 63) / 64);
-    return std::min(want, maxs);
+    return std::min(want, max_splits(B));
+}
+
+int fwd_splits(const spgm_plan *p, int B) {
+    const auto it = p->tuned.find(B);
+    return it != p->tuned.end() ? it->second.first : default_splits(p, B);
+}
+
+int adj_splits(const spgm_plan *p, int B) {
+    const auto it = p->tuned.find(B);
+    return it != p->tuned.end() ? it->second.second : default_splits(p, B);
 }
 
 // A captured solve graph holds workspace pointers: drop it whenever the workspace moves.
@@ -954,7 +971,7 @@ void drop_graph(spgm_plan *p) {
 }
 
 int ensure_workspace(spgm_plan *p, int B) {
-    const int splits = row_splits(p, B);
+    const int splits = adj_splits(p, B);
     if (B <= p->ws_B && splits <= p->ws_splits) return SPGM_OK;
     drop_graph(p);
     const int nb = std::max(B, p->ws_B);
@@ -1031,7 +1048,7 @@ hipEvent_t *timing_slot(spgm_plan *p, std::vector<hipEvent_t> &pool, size_t &use
 }
 
 int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, hipStream_t st) {
-    const int splits = row_splits(p, B);
+    const int splits = fwd_splits(p, B);
     const int rpw = (B + splits - 1) / splits;
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
     if (ev) hipEventRecord(ev[0], st);
@@ -1051,7 +1068,7 @@ int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, 
 }
 
 int run_adjoint_partials(spgm_plan *p, const int4 *srt, int B, hipStream_t st) {
-    const int splits = row_splits(p, B);
+    const int splits = adj_splits(p, B);
     const int rpw = (B + splits - 1) / splits;
     hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
     if (ev) hipEventRecord(ev[0], st);
@@ -1087,7 +1104,7 @@ int step_sorted(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const
     if ((rc = run_forward_partials(p, srt, s, B, st))) return rc;
     if ((rc = run_row_reduce(p, srt, rows, B, y, nullptr, p->d_rs, st))) return rc;
     if ((rc = run_adjoint_partials(p, srt, B, st))) return rc;
-    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, row_splits(p, B), (int)p->N, nullptr, s,
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, nullptr, s,
                                                              eta / (float)B, alpha);
     return launch_check("column reduce");
 }
@@ -1293,7 +1310,7 @@ int spgm_adjoint(spgm_plan *p, const int32_t *rows, int32_t B, const void *r, vo
     k_gather_scale<<<(B + 255) / 256, 256, 0, st>>>(p->geo, p->d_srt, B, (const float2 *)r, p->d_rs);
     if ((rc = launch_check("gather"))) return rc;
     if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
-    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, row_splits(p, B), (int)p->N, (float2 *)g,
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, (float2 *)g,
                                                              nullptr, 0.f, 0.f);
     if ((rc = launch_check("column reduce"))) return rc;
     return ok();
@@ -1424,7 +1441,7 @@ int spgm_unrolled_vjp_step(spgm_plan *p, const int32_t *rows, int32_t B, const v
     hipStream_t st = (hipStream_t)stream;
     const int N = (int)p->N;
     float2 *g = p->d_vjp, *zbar = p->d_vjp + N, *h = p->d_vjp + 2 * (size_t)N;
-    const int splits = row_splits(p, B);
+    const int splits = adj_splits(p, B);
     const int nb = (N + kVjpThreads - 1) / kVjpThreads;
     const float step = eta / (float)B;
     // recompute g = A_B^H (A_B s - y_B) at the iterate entering the iteration
@@ -1448,6 +1465,167 @@ int spgm_unrolled_vjp_step(spgm_plan *p, const int32_t *rows, int32_t B, const v
     if ((rc = launch_check("axpy"))) return rc;
     k_sum_partials<<<1, 256, 0, st>>>(p->d_vjp_part, nb, eta_bar, tau_bar);
     if ((rc = launch_check("sum partials"))) return rc;
+    return ok();
+}
+
+// ------------------------------------------------------------------------------------------
+// Autotuner: time the two tile kernels over candidate row splits (minibatch rows per
+// work-group) and keep the fastest per kernel; results are cached in a small JSON file.
+// ------------------------------------------------------------------------------------------
+static std::string tune_key(const spgm_plan *p, int B) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::ostringstream k;
+    k << arch << "|phase" << p->phase_mode << "|T" << p->geo.T << "|R" << p->geo.R << "|F" << p->geo.F << "|grid"
+      << p->geo.nx << "x" << p->geo.ny << "x" << p->geo.nz << "|B" << B;
+    return k.str();
+}
+
+// The cache is a flat JSON object {"key": [fwd_splits, adj_splits, fwd_ms, adj_ms], ...}.
+static std::map<std::string, std::vector<double>> read_cache(const std::string &path) {
+    std::map<std::string, std::vector<double>> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t i = 0;
+    while ((i = t.find('"', i)) != std::string::npos) {
+        const size_t j = t.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = t.substr(i + 1, j - i - 1);
+        const size_t a = t.find('[', j), b = t.find(']', j);
+        if (a == std::string::npos || b == std::string::npos) break;
+        std::vector<double> v;
+        std::stringstream vs(t.substr(a + 1, b - a - 1));
+        std::string item;
+        while (std::getline(vs, item, ',')) v.push_back(std::atof(item.c_str()));
+        out[key] = v;
+        i = b + 1;
+    }
+    return out;
+}
+
+static void write_cache(const std::string &path, const std::map<std::string, std::vector<double>> &c) {
+    std::ofstream f(path + ".tmp");
+    if (!f) return;
+    f << "{\n";
+    size_t n = 0;
+    for (const auto &kv : c) {
+        f << "  \"" << kv.first << "\": [";
+        for (size_t i = 0; i < kv.second.size(); ++i) f << (i ? ", " : "") << kv.second[i];
+        f << "]" << (++n < c.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+    f.close();
+    std::rename((path + ".tmp").c_str(), path.c_str());
+}
+
+int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t *fwd_out, int32_t *adj_out) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm_plan_autotune: plan is NULL");
+    if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm_plan_autotune: B=%d outside [1, %d]", B, kMaxB);
+    DeviceGuard guard(p->device);
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
+    const std::string key = tune_key(p, B);
+    std::map<std::string, std::vector<double>> cache;
+    if (!path.empty()) cache = read_cache(path);
+    const auto hit = cache.find(key);
+    if (hit != cache.end() && hit->second.size() >= 2) {
+        p->tuned[B] = {std::max(1, std::min((int)hit->second[0], max_splits(B))),
+                       std::max(1, std::min((int)hit->second[1], max_splits(B)))};
+    } else {
+        // candidates: 1, 2, 3, 4, 6, 8, 12, 16, ... rows per work-group >= 64
+        std::vector<int> cand;
+        for (int c = 1; c <= max_splits(B); c = (c < 4 ? c + 1 : c + c / 2)) cand.push_back(c);
+        if (cand.back() != max_splits(B)) cand.push_back(max_splits(B));
+        if (cand.size() > 10) cand.erase(cand.begin() + 9, cand.end() - 1);
+        // timing inputs: uniform pseudo-random rows (xorshift) and a random vector
+        std::vector<int32_t> hrows(B);
+        uint64_t x = 0x9E3779B97F4A7C15ull ^ (uint64_t)B;
+        for (int i = 0; i < B; ++i) {
+            x ^= x << 13;
+            x ^= x >> 7;
+            x ^= x << 17;
+            hrows[i] = (int32_t)(x % (uint64_t)p->M);
+        }
+        std::vector<float2> hs(p->N);
+        for (int64_t n = 0; n < p->N; ++n) {
+            x ^= x << 13;
+            x ^= x >> 7;
+            x ^= x << 17;
+            hs[n] = make_float2((float)((x >> 11) % 2001) / 1000.f - 1.f, (float)((x >> 33) % 2001) / 1000.f - 1.f);
+        }
+        int32_t *drows = nullptr;
+        float2 *ds = nullptr;
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int rc = SPGM_OK;
+        const int max_c = cand.back();
+        if (hipMalloc(&drows, sizeof(int32_t) * B) != hipSuccess || hipMalloc(&ds, sizeof(float2) * p->N) != hipSuccess ||
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess)
+            rc = fail(SPGM_E_NOMEM, "spgm_plan_autotune: allocation failed");
+        if (!rc && (hipMemcpy(drows, hrows.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(ds, hs.data(), sizeof(float2) * p->N, hipMemcpyHostToDevice) != hipSuccess))
+            rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune: copy failed");
+        // size the workspace for the largest candidate
+        if (!rc) {
+            p->tuned[B] = {max_c, max_c};
+            rc = ensure_workspace(p, B);
+        }
+        if (!rc) rc = run_sort(p, drows, B, 1, p->d_srt, st);
+        double best_f = 1e30, best_a = 1e30;
+        int bf = 1, ba = 1;
+        const bool timing = p->timing;
+        p->timing = false;
+        for (size_t ci = 0; !rc && ci < cand.size(); ++ci) {
+            p->tuned[B] = {cand[ci], cand[ci]};
+            for (int which = 0; which < 2 && !rc; ++which) {
+                float best = 1e30f;
+                for (int rep = 0; rep < 4 && !rc; ++rep) {
+                    hipEventRecord(e0, st);
+                    rc = which == 0 ? run_forward_partials(p, p->d_srt, ds, B, st) : run_adjoint_partials(p, p->d_srt, B, st);
+                    hipEventRecord(e1, st);
+                    hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (rep > 0) best = std::min(best, ms);  // first launch warms up
+                }
+                if (which == 0 && best < best_f) {
+                    best_f = best;
+                    bf = cand[ci];
+                }
+                if (which == 1 && best < best_a) {
+                    best_a = best;
+                    ba = cand[ci];
+                }
+            }
+        }
+        p->timing = timing;
+        hipFree(drows);
+        hipFree(ds);
+        if (st) hipStreamDestroy(st);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (rc) {
+            p->tuned.erase(B);
+            return rc;
+        }
+        p->tuned[B] = {bf, ba};
+        if (!path.empty()) {
+            cache[key] = {(double)bf, (double)ba, best_f, best_a};
+            write_cache(path, cache);
+        }
+    }
+    int rc;
+    if ((rc = ensure_workspace(p, B))) return rc;
+    drop_graph(p);  // launch shapes changed
+    if (fwd_out) *fwd_out = p->tuned[B].first;
+    if (adj_out) *adj_out = p->tuned[B].second;
     return ok();
 }
 

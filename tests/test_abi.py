@@ -89,3 +89,7 @@ def test_product_path_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(bd, "_LIB", None)
     with pytest.raises(RuntimeError, match="not built"):
         bd.load_library(str(tmp_path / "missing.so"))
+
+
+def test_autotune_rejects_null_plan(lib):
+    assert lib.spgm_plan_autotune(None, 16, None, None, None) == bd.SPGM_E_INVALID
