@@ -147,6 +147,34 @@ int spgm_unrolled_vjp_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, co
 int spgm_plan_autotune(spgm_plan *plan, int32_t B, const char *cache_path, int32_t *fwd_splits,
                        int32_t *adj_splits);
 
+/* Ragged batches of independent scenes (each with its own array, band and grid) advanced
+ * together: every SPGM iteration of every scene is one launch per phase (sort, forward tile,
+ * row reduction, adjoint tile, column reduction with the prox step).  The tile phases walk a
+ * work list of (scene, voxel brick, row range) items ordered longest first with persistent
+ * work-groups, so scenes of very different sizes share the chip. */
+typedef struct spgm_batch spgm_batch;
+
+/* One plan per geometry (geoms: host array of n spgm_geometry, same rules as spgm_plan_create,
+ * one phase mode for all).  Synchronous. */
+int spgm_batch_create(spgm_batch **out, const spgm_geometry *geoms, int32_t n, int32_t phase_mode);
+int spgm_batch_destroy(spgm_batch *batch);
+
+/* The plan of scene i (owned by the batch; usable with every spgm_plan call). */
+int spgm_batch_plan(spgm_batch *batch, int32_t i, spgm_plan **plan);
+
+/* `iters` SPGM iterations of every scene (the update of spgm_step).  Host arrays of length n:
+ * B[i] rows per minibatch of scene i; rows_d[i] device int32[iters * B[i]] (iteration k uses
+ * rows_d[i][k*B[i] ...]); y_d[i] device complex64[M_i]; s_d[i] device complex64[N_i] in/out;
+ * eta[i] > 0, alpha[i] >= 0.  use_graph != 0 captures the launches of the whole solve into a
+ * HIP graph and launches it once (one submission; same results).  Grows the batch's workspace
+ * with hipMalloc when needed. */
+int spgm_batch_solve(spgm_batch *batch, int32_t iters, const int32_t *B, const int32_t *const *rows_d,
+                     const void *const *y_d, void *const *s_d, const float *eta, const float *alpha,
+                     int32_t use_graph, void *stream);
+
+/* Device-detected row errors of the batch's earlier solves (as spgm_plan_status). */
+int spgm_batch_status(spgm_batch *batch, int32_t *status);
+
 /* Device-detected errors of earlier calls (currently SPGM_E_BADROW).  Synchronises the plan's
  * device, writes the sticky status to *status (SPGM_OK if none) and clears it. */
 int spgm_plan_status(spgm_plan *plan, int32_t *status);

@@ -29,7 +29,8 @@ PHASE_NAIVE32 = 2
 
 EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
             "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
-            "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph", "spgm_plan_autotune")
+            "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph", "spgm_plan_autotune",
+            "spgm_batch_create", "spgm_batch_destroy", "spgm_batch_plan", "spgm_batch_solve", "spgm_batch_status")
 
 _dp = C.POINTER(C.c_double)
 
@@ -72,6 +73,12 @@ def load_library(path: str = LIB_PATH):
         "spgm_solve": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_solve_graph": [vp, vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_plan_autotune": [vp, i32, C.c_char_p, C.POINTER(i32), C.POINTER(i32)],
+        "spgm_batch_create": [C.POINTER(vp), C.POINTER(SpgmGeometry), i32, i32],
+        "spgm_batch_destroy": [vp],
+        "spgm_batch_plan": [vp, i32, C.POINTER(vp)],
+        "spgm_batch_solve": [vp, i32, C.POINTER(i32), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                             C.POINTER(f32), C.POINTER(f32), i32, vp],
+        "spgm_batch_status": [vp, C.POINTER(i32)],
         "spgm_plan_status": [vp, C.POINTER(i32)],
         "spgm_plan_timing": [vp, i32],
         "spgm_unrolled_vjp_step": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
@@ -141,12 +148,16 @@ def _dev(t, dtype, name, numel=None):
 class Plan:
     """A plan (``spgm_plan``) for one geometry on the current device."""
 
-    def __init__(self, geom, phase_mode: int = PHASE_COMP32):
+    def __init__(self, geom, phase_mode: int = PHASE_COMP32, _handle=None):
         lib = load_library()
-        g, keep = make_geometry_struct(geom)
-        h = C.c_void_p()
-        _check(lib.spgm_plan_create(C.byref(h), C.byref(g), int(phase_mode)))
-        del keep
+        self._owned = _handle is None
+        if _handle is None:
+            g, keep = make_geometry_struct(geom)
+            h = C.c_void_p()
+            _check(lib.spgm_plan_create(C.byref(h), C.byref(g), int(phase_mode)))
+            del keep
+        else:
+            h = _handle
         self._h = h
         self._lib = lib
         M, N = C.c_int64(), C.c_int64()
@@ -155,7 +166,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.spgm_plan_destroy(self._h)
+            if self._owned:
+                self._lib.spgm_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -263,3 +275,68 @@ class Plan:
     solve = spgm_solve
     status = spgm_plan_status
     autotune = spgm_plan_autotune
+
+
+class Batch:
+    """A ragged batch (``spgm_batch``) of independent scenes advanced by one launch per phase."""
+
+    def __init__(self, geoms, phase_mode: int = PHASE_COMP32):
+        lib = load_library()
+        n = len(geoms)
+        arr = (SpgmGeometry * n)()
+        keep = []
+        for i, geom in enumerate(geoms):
+            g, k = make_geometry_struct(geom)
+            arr[i] = g
+            keep.append(k)
+        h = C.c_void_p()
+        _check(lib.spgm_batch_create(C.byref(h), arr, n, int(phase_mode)))
+        del keep
+        self._h, self._lib, self.n = h, lib, n
+        self.plans = []
+        for i in range(n):
+            ph = C.c_void_p()
+            _check(lib.spgm_batch_plan(h, i, C.byref(ph)))
+            self.plans.append(Plan(None, _handle=ph))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for p in self.plans:
+                p.close()
+            self._lib.spgm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def spgm_batch_solve(self, rows_tables, ys, ss, etas, alphas, use_graph=False, stream=None):
+        """rows_tables[i]: int32 (iters, B_i); ys[i]: complex64 (M_i,); ss[i]: complex64 (N_i,) in/out."""
+        import torch
+        n = self.n
+        if not (len(rows_tables) == len(ys) == len(ss) == len(etas) == len(alphas) == n):
+            raise ValueError("one entry per scene is required")
+        iters = int(rows_tables[0].shape[0])
+        Bs = (C.c_int32 * n)()
+        rp, yp, sp = (C.c_void_p * n)(), (C.c_void_p * n)(), (C.c_void_p * n)()
+        for i in range(n):
+            if rows_tables[i].dim() != 2 or int(rows_tables[i].shape[0]) != iters:
+                raise ValueError("every rows table must be (iters, B_i) with the same iters")
+            Bs[i] = int(rows_tables[i].shape[1])
+            rp[i] = _dev(rows_tables[i], torch.int32, "rows")
+            yp[i] = _dev(ys[i], torch.complex64, "y", self.plans[i].M)
+            sp[i] = _dev(ss[i], torch.complex64, "s", self.plans[i].N)
+        ea = (C.c_float * n)(*[float(v) for v in etas])
+        aa = (C.c_float * n)(*[float(v) for v in alphas])
+        _check(self._lib.spgm_batch_solve(self._h, iters, Bs, rp, yp, sp, ea, aa, 1 if use_graph else 0,
+                                          _stream_ptr(stream)))
+
+    def spgm_batch_status(self):
+        st = C.c_int32()
+        _check(self._lib.spgm_batch_status(self._h, C.byref(st)))
+        return st.value
+
+    solve = spgm_batch_solve
+    status = spgm_batch_status

@@ -181,12 +181,9 @@ __device__ __forceinline__ int ant_of_l(const Geo &g, int li) { return g.g_is_tx
 // 1. Sort the minibatch by (G, L, f, original position), one work-group per chunk of rows.
 //    Output srt[i] = (original position j, f, G index, L index) of the i-th sorted row.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void k_sort_rows(Geo g, const int32_t *__restrict__ rows, int B,
-                                                            int4 *__restrict__ srt, int *__restrict__ status) {
-    extern __shared__ unsigned long long keys[];  // next power of two >= min(B, kSortChunk)
-    rows += (size_t)blockIdx.y * B;               // minibatch blockIdx.y of a batched sort
-    srt += (size_t)blockIdx.y * B;
-    const int c0 = blockIdx.x * kSortChunk;
+__device__ __forceinline__ void sort_rows_body(const Geo &g, unsigned long long *keys, const int32_t *__restrict__ rows,
+                                               int B, int4 *__restrict__ srt, int *__restrict__ status, int chunk) {
+    const int c0 = chunk * kSortChunk;
     const int n = min(kSortChunk, B - c0);
     int p2 = 2;
     while (p2 < n) p2 <<= 1;
@@ -233,6 +230,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_rows(Geo g, const int32_t
         const int gi = (int)(pair / (unsigned int)g.nL);
         srt[c0 + i] = make_int4(c0 + j, f, gi, li);
     }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_rows(Geo g, const int32_t *__restrict__ rows, int B,
+                                                            int4 *__restrict__ srt, int *__restrict__ status) {
+    extern __shared__ unsigned long long keys[];  // next power of two >= min(B, kSortChunk)
+    // minibatch blockIdx.y of a batched sort
+    sort_rows_body(g, keys, rows + (size_t)blockIdx.y * B, B, srt + (size_t)blockIdx.y * B, status, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -441,16 +445,15 @@ __device__ __forceinline__ int stage_rows(const Geo &g, const TileSmem &sm, cons
 // ------------------------------------------------------------------------------------------
 // 2. Forward partials: part[tile][i] = sum over brick voxels of (A_{row i, n} / q_f) s_n.
 // ------------------------------------------------------------------------------------------
+// Body shared by the single-plan launch (one brick x row range per work-group) and the
+// work-list launch over many scenes: brick `tile`, sorted rows [r0, r1).
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
-                                                       const float2 *__restrict__ s, float2 *__restrict__ part) {
+__device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile, int r0, int r1,
+                                              const int4 *__restrict__ srt, int B, const float2 *__restrict__ s,
+                                              float2 *__restrict__ part) {
     using P = Phase<MODE>;
     using DT = typename P::D;
-    extern __shared__ __align__(16) char smem[];
     const TileSmem sm = carve(smem, g);
-    const int tile = blockIdx.x;
-    const int r0 = blockIdx.y * rows_per_wg;
-    const int r1 = min(B, r0 + rows_per_wg);
     int bx, by, bz;
     brick_of(g, tile, bx, by, bz);
     stage_tile<MODE>(g, sm, bx, by, bz);
@@ -564,21 +567,27 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
     }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
+                                                       const float2 *__restrict__ s, float2 *__restrict__ part) {
+    extern __shared__ __align__(16) char smem[];
+    const int r0 = blockIdx.y * rows_per_wg;
+    fwd_tile_body<MODE>(g, smem, blockIdx.x, r0, min(B, r0 + rows_per_wg), srt, B, s, part);
+}
+
 // ------------------------------------------------------------------------------------------
 // 3. Row reduction: v_i = q_f * sum_tiles part[tile][i]  (minus y_m when y is given).
 //    out_user[j] = v (caller order); out_scaled[i] = conj(q_f) * v (sorted order, adjoint input).
 // ------------------------------------------------------------------------------------------
 constexpr int kRedGroups = 16;  // tile groups per row-reduction work-group (64 rows x 16)
 
-__global__ __launch_bounds__(64 * kRedGroups) void k_row_reduce(Geo g, const float2 *__restrict__ part, int n_tiles,
-                                                               int B, const int4 *__restrict__ srt,
-                                                               const int32_t *__restrict__ rows,
-                                                               const float2 *__restrict__ y,
-                                                               float2 *__restrict__ out_user,
-                                                               float2 *__restrict__ out_scaled) {
+__device__ __forceinline__ void row_reduce_body(const Geo &g, const float2 *__restrict__ part, int n_tiles, int B,
+                                                const int4 *__restrict__ srt, const int32_t *__restrict__ rows,
+                                                const float2 *__restrict__ y, float2 *__restrict__ out_user,
+                                                float2 *__restrict__ out_scaled, int row0) {
     __shared__ float2 red[kRedGroups][64];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + tx;
+    const int i = row0 + tx;
     float ar = 0.f, ai = 0.f;
     if (i < B) {
         for (int t = ty; t < n_tiles; t += kRedGroups) {
@@ -613,6 +622,15 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_row_reduce(Geo g, const flo
     }
 }
 
+__global__ __launch_bounds__(64 * kRedGroups) void k_row_reduce(Geo g, const float2 *__restrict__ part, int n_tiles,
+                                                               int B, const int4 *__restrict__ srt,
+                                                               const int32_t *__restrict__ rows,
+                                                               const float2 *__restrict__ y,
+                                                               float2 *__restrict__ out_user,
+                                                               float2 *__restrict__ out_scaled) {
+    row_reduce_body(g, part, n_tiles, B, srt, rows, y, out_user, out_scaled, blockIdx.x * 64);
+}
+
 // Adjoint input for a caller-supplied residual: out_scaled[i] = conj(q_f) * r[j_i].
 __global__ __launch_bounds__(256) void k_gather_scale(Geo g, const int4 *__restrict__ srt, int B,
                                                       const float2 *__restrict__ r, float2 *__restrict__ out_scaled) {
@@ -632,16 +650,12 @@ __global__ __launch_bounds__(256) void k_gather_scale(Geo g, const int4 *__restr
 //    summed first and scaled once when the pair ends.
 // ------------------------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
-                                                       const float2 *__restrict__ rs, float2 *__restrict__ gpart,
-                                                       int N) {
+__device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile, int split, int r0, int r1,
+                                              const int4 *__restrict__ srt, int B, const float2 *__restrict__ rs,
+                                              float2 *__restrict__ gpart, int N) {
     using P = Phase<MODE>;
     using DT = typename P::D;
-    extern __shared__ __align__(16) char smem[];
     const TileSmem sm = carve(smem, g);
-    const int tile = blockIdx.x;
-    const int r0 = blockIdx.y * rows_per_wg;
-    const int r1 = min(B, r0 + rows_per_wg);
     int bx, by, bz;
     brick_of(g, tile, bx, by, bz);
     stage_tile<MODE>(g, sm, bx, by, bz);
@@ -739,17 +753,25 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
             acc.x += red[w * kBrick + v].x;
             acc.y += red[w * kBrick + v].y;
         }
-        gpart[(size_t)blockIdx.y * N + ((size_t)iz * g.ny + iy) * g.nx + ix] = acc;
+        gpart[(size_t)split * N + ((size_t)iz * g.ny + iy) * g.nx + ix] = acc;
     }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
+                                                       const float2 *__restrict__ rs, float2 *__restrict__ gpart,
+                                                       int N) {
+    extern __shared__ __align__(16) char smem[];
+    const int r0 = blockIdx.y * rows_per_wg;
+    adj_tile_body<MODE>(g, smem, blockIdx.x, blockIdx.y, r0, min(B, r0 + rows_per_wg), srt, B, rs, gpart, N);
 }
 
 // ------------------------------------------------------------------------------------------
 // 5. Column reduction over row splits; optional gradient step and complex soft threshold.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_col_reduce(const float2 *__restrict__ gpart, int nsplit, int N,
-                                                    float2 *__restrict__ g_out, float2 *__restrict__ s, float step,
-                                                    float alpha) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void col_reduce_body(const float2 *__restrict__ gpart, int nsplit, int N,
+                                                float2 *__restrict__ g_out, float2 *__restrict__ s, float step,
+                                                float alpha, int n) {
     if (n >= N) return;
     float gr = 0.f, gi = 0.f;
     for (int k = 0; k < nsplit; ++k) {
@@ -773,6 +795,84 @@ __global__ __launch_bounds__(256) void k_col_reduce(const float2 *__restrict__ g
         }
         s[n] = v;
     }
+}
+
+__global__ __launch_bounds__(256) void k_col_reduce(const float2 *__restrict__ gpart, int nsplit, int N,
+                                                    float2 *__restrict__ g_out, float2 *__restrict__ s, float step,
+                                                    float alpha) {
+    col_reduce_body(gpart, nsplit, N, g_out, s, step, alpha, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ------------------------------------------------------------------------------------------
+// Ragged batches: many scenes advanced by one launch per phase.  Each scene has a descriptor
+// in device memory; tile work is a list of (scene, brick, row range) items ordered longest
+// first, walked by persistent work-groups in a fixed round-robin order.
+// ------------------------------------------------------------------------------------------
+struct SceneDev {
+    Geo geo;
+    int B, rpw, n_tiles, splits, N;
+    const int32_t *rows;  // iteration k uses rows + k * B
+    int4 *srt;            // [B]
+    const float2 *y;      // [M]
+    float2 *s;            // [N]
+    float2 *part;         // [n_tiles][B]
+    float2 *rs;           // [B]
+    float2 *gpart;        // [splits][N]
+    float step, alpha;    // eta / B, threshold
+};
+
+__device__ __forceinline__ int4 uniform4(int4 v) {
+    return make_int4(uniform(v.x), uniform(v.y), uniform(v.z), uniform(v.w));
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scenes(const SceneDev *__restrict__ sc, int iter,
+                                                              int *__restrict__ status) {
+    extern __shared__ unsigned long long keys[];
+    const SceneDev &d = sc[blockIdx.y];
+    if ((int)blockIdx.x * kSortChunk >= d.B) return;
+    sort_rows_body(d.geo, keys, d.rows + (size_t)iter * d.B, d.B, d.srt, status, blockIdx.x);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_fwd_items(const SceneDev *__restrict__ sc, const int4 *__restrict__ items,
+                                                        int n_items) {
+    extern __shared__ __align__(16) char smem[];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 w = uniform4(items[it]);  // (scene, brick, split, cost)
+        const SceneDev &d = sc[w.x];
+        const int r0 = w.z * d.rpw;
+        fwd_tile_body<MODE>(d.geo, smem, w.y, r0, min(d.B, r0 + d.rpw), d.srt, d.B, d.s, d.part);
+        __syncthreads();
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_adj_items(const SceneDev *__restrict__ sc, const int4 *__restrict__ items,
+                                                        int n_items) {
+    extern __shared__ __align__(16) char smem[];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 w = uniform4(items[it]);
+        const SceneDev &d = sc[w.x];
+        const int r0 = w.z * d.rpw;
+        adj_tile_body<MODE>(d.geo, smem, w.y, w.z, r0, min(d.B, r0 + d.rpw), d.srt, d.B, d.rs, d.gpart, d.N);
+        __syncthreads();
+    }
+}
+
+// blocks[b] = (scene, first row) of 64-row blocks over every scene
+__global__ __launch_bounds__(64 * kRedGroups) void k_row_reduce_scenes(const SceneDev *__restrict__ sc,
+                                                                      const int2 *__restrict__ blocks, int iter) {
+    const int2 b = blocks[blockIdx.x];
+    const SceneDev &d = sc[b.x];
+    row_reduce_body(d.geo, d.part, d.n_tiles, d.B, d.srt, d.rows + (size_t)iter * d.B, d.y, nullptr, d.rs, b.y);
+}
+
+// blocks[b] = (scene, first voxel) of 256-voxel blocks: gradient step and threshold
+__global__ __launch_bounds__(256) void k_col_reduce_scenes(const SceneDev *__restrict__ sc,
+                                                           const int2 *__restrict__ blocks) {
+    const int2 b = blocks[blockIdx.x];
+    const SceneDev &d = sc[b.x];
+    col_reduce_body(d.gpart, d.splits, d.N, nullptr, d.s, d.step, d.alpha, b.y + threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -935,6 +1035,23 @@ struct spgm_plan {
     size_t n_fwd = 0, n_adj = 0;
     // autotuned row splits per minibatch size: B -> (forward, adjoint)
     std::map<int, std::pair<int, int>> tuned;
+};
+
+// A batch of independent scenes (one plan each) advanced together.
+struct spgm_batch {
+    int device = 0;
+    int phase_mode = 0;
+    std::vector<spgm_plan *> plans;
+    hipStream_t cap_stream = nullptr;
+    int *d_status = nullptr;
+    SceneDev *d_scenes = nullptr;
+    size_t scenes_cap = 0;
+    int4 *d_items = nullptr;
+    size_t items_cap = 0;
+    int2 *d_blocks = nullptr;  // row blocks then voxel blocks
+    size_t blocks_cap = 0;
+    char *d_ws = nullptr;
+    size_t ws_cap = 0;
 };
 
 namespace {
@@ -1626,6 +1743,233 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
     drop_graph(p);  // launch shapes changed
     if (fwd_out) *fwd_out = p->tuned[B].first;
     if (adj_out) *adj_out = p->tuned[B].second;
+    return ok();
+}
+
+// ------------------------------------------------------------------------------------------
+// Ragged batches
+// ------------------------------------------------------------------------------------------
+int spgm_batch_create(spgm_batch **out, const spgm_geometry *geoms, int32_t n, int32_t phase_mode) {
+    if (!out) return fail(SPGM_E_INVALID, "spgm_batch_create: out is NULL");
+    *out = nullptr;
+    if (!geoms || n < 1) return fail(SPGM_E_INVALID, "spgm_batch_create: need n >= 1 geometries");
+    spgm_batch *b = new spgm_batch();
+    b->phase_mode = phase_mode;
+    for (int i = 0; i < n; ++i) {
+        spgm_plan *p = nullptr;
+        const int rc = spgm_plan_create(&p, geoms + i, phase_mode);
+        if (rc) {
+            const std::string msg = g_last_error;
+            spgm_batch_destroy(b);
+            return fail(rc, "spgm_batch_create: scene %d: %s", i, msg.c_str());
+        }
+        b->plans.push_back(p);
+    }
+    b->device = b->plans[0]->device;
+    DeviceGuard guard(b->device);
+    if (hipMalloc(&b->d_status, sizeof(int)) != hipSuccess || hipMemset(b->d_status, 0, sizeof(int)) != hipSuccess) {
+        spgm_batch_destroy(b);
+        return fail(SPGM_E_NOMEM, "spgm_batch_create: allocation failed");
+    }
+    *out = b;
+    return ok();
+}
+
+int spgm_batch_destroy(spgm_batch *b) {
+    if (!b) return ok();
+    {
+        DeviceGuard guard(b->device);
+        hipDeviceSynchronize();
+        hipFree(b->d_status);
+        hipFree(b->d_scenes);
+        hipFree(b->d_items);
+        hipFree(b->d_blocks);
+        hipFree(b->d_ws);
+        if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    }
+    for (spgm_plan *p : b->plans) spgm_plan_destroy(p);
+    delete b;
+    return ok();
+}
+
+int spgm_batch_plan(spgm_batch *b, int32_t i, spgm_plan **plan) {
+    if (!b || !plan || i < 0 || i >= (int)b->plans.size()) return fail(SPGM_E_INVALID, "spgm_batch_plan: bad argument");
+    *plan = b->plans[i];
+    return ok();
+}
+
+extern "C++" {
+template <typename T> static int grow(T *&ptr, size_t &cap, size_t need) {
+    if (need <= cap) return SPGM_OK;
+    hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    if (hipMalloc(&ptr, sizeof(T) * need) != hipSuccess) return fail(SPGM_E_NOMEM, "spgm_batch: allocation failed");
+    cap = need;
+    return SPGM_OK;
+}
+}
+
+static int batch_launches(spgm_batch *b, int iters, int n_items, int grid_items, size_t lds, int max_chunks, int p2,
+                          int n_rblocks, int n_cblocks, hipStream_t st) {
+    const int n = (int)b->plans.size();
+    const int mode = b->phase_mode;
+    for (int k = 0; k < iters; ++k) {
+        k_sort_scenes<<<dim3(max_chunks, n), kSortThreads, sizeof(unsigned long long) * p2, st>>>(b->d_scenes, k,
+                                                                                                 b->d_status);
+        if (mode == SPGM_PHASE_F64)
+            k_fwd_items<SPGM_PHASE_F64><<<grid_items, kThreads, lds, st>>>(b->d_scenes, b->d_items, n_items);
+        else if (mode == SPGM_PHASE_NAIVE32)
+            k_fwd_items<SPGM_PHASE_NAIVE32><<<grid_items, kThreads, lds, st>>>(b->d_scenes, b->d_items, n_items);
+        else
+            k_fwd_items<SPGM_PHASE_COMP32><<<grid_items, kThreads, lds, st>>>(b->d_scenes, b->d_items, n_items);
+        k_row_reduce_scenes<<<n_rblocks, 64 * kRedGroups, 0, st>>>(b->d_scenes, b->d_blocks, k);
+        if (mode == SPGM_PHASE_F64)
+            k_adj_items<SPGM_PHASE_F64><<<grid_items, kThreads, lds, st>>>(b->d_scenes, b->d_items, n_items);
+        else if (mode == SPGM_PHASE_NAIVE32)
+            k_adj_items<SPGM_PHASE_NAIVE32><<<grid_items, kThreads, lds, st>>>(b->d_scenes, b->d_items, n_items);
+        else
+            k_adj_items<SPGM_PHASE_COMP32><<<grid_items, kThreads, lds, st>>>(b->d_scenes, b->d_items, n_items);
+        k_col_reduce_scenes<<<n_cblocks, 256, 0, st>>>(b->d_scenes, b->d_blocks + n_rblocks);
+        int rc;
+        if ((rc = launch_check("batch iteration"))) return rc;
+    }
+    return SPGM_OK;
+}
+
+int spgm_batch_solve(spgm_batch *b, int32_t iters, const int32_t *B, const int32_t *const *rows, const void *const *y,
+                     void *const *s, const float *eta, const float *alpha, int32_t use_graph, void *stream) {
+    if (!b) return fail(SPGM_E_INVALID, "spgm_batch_solve: batch is NULL");
+    if (!B || !rows || !y || !s || !eta || !alpha) return fail(SPGM_E_INVALID, "spgm_batch_solve: NULL argument array");
+    if (iters < 0) return fail(SPGM_E_INVALID, "spgm_batch_solve: iters must be >= 0");
+    const int n = (int)b->plans.size();
+    for (int i = 0; i < n; ++i) {
+        if (B[i] < 1 || B[i] > kMaxB) return fail(SPGM_E_INVALID, "spgm_batch_solve: scene %d: B=%d out of range", i, B[i]);
+        if (!rows[i] || !y[i] || !s[i]) return fail(SPGM_E_INVALID, "spgm_batch_solve: scene %d: NULL pointer", i);
+        if (!(std::isfinite(eta[i]) && eta[i] > 0) || !(std::isfinite(alpha[i]) && alpha[i] >= 0))
+            return fail(SPGM_E_INVALID, "spgm_batch_solve: scene %d: eta must be > 0 and alpha >= 0", i);
+    }
+    if (iters == 0) return ok();
+    DeviceGuard guard(b->device);
+    // Layout of the scenes' workspace and the work list.
+    std::vector<SceneDev> h(n);
+    std::vector<size_t> off(n);
+    size_t ws = 0;
+    auto take = [&ws](size_t bytes) {
+        const size_t o = ws;
+        ws += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    struct Item { int4 v; long cost; };
+    std::vector<Item> items;
+    std::vector<int2> rblocks, cblocks;
+    size_t lds = 0;
+    int max_chunks = 1, p2 = 2;
+    for (int i = 0; i < n; ++i) {
+        spgm_plan *p = b->plans[i];
+        SceneDev &d = h[i];
+        d.geo = p->geo;
+        d.B = B[i];
+        d.splits = std::max(1, (B[i] + 1023) / 1024);
+        d.rpw = (B[i] + d.splits - 1) / d.splits;
+        d.n_tiles = p->n_tiles;
+        d.N = (int)p->N;
+        d.rows = rows[i];
+        d.y = (const float2 *)y[i];
+        d.s = (float2 *)s[i];
+        d.step = eta[i] / (float)B[i];
+        d.alpha = alpha[i];
+        off[i] = take(sizeof(int4) * B[i]);
+        take(sizeof(float2) * (size_t)d.n_tiles * B[i]);
+        take(sizeof(float2) * B[i]);
+        take(sizeof(float2) * (size_t)d.splits * d.N);
+        for (int t = 0; t < d.n_tiles; ++t)
+            for (int sp = 0; sp < d.splits; ++sp) {
+                const int rows_here = std::min(d.rpw, B[i] - sp * d.rpw);
+                if (rows_here > 0) items.push_back({make_int4(i, t, sp, 0), (long)rows_here});
+            }
+        for (int r = 0; r < B[i]; r += 64) rblocks.push_back(make_int2(i, r));
+        for (int v = 0; v < d.N; v += 256) cblocks.push_back(make_int2(i, v));
+        lds = std::max(lds, p->lds_bytes);
+        max_chunks = std::max(max_chunks, (B[i] + kSortChunk - 1) / kSortChunk);
+        while (p2 < std::min(B[i], kSortChunk)) p2 <<= 1;
+    }
+    // longest first; ties keep scene/brick order (deterministic)
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &c) { return a.cost > c.cost; });
+    std::vector<int4> hitems(items.size());
+    for (size_t k = 0; k < items.size(); ++k) hitems[k] = items[k].v;
+    int rc;
+    if ((rc = grow(b->d_ws, b->ws_cap, ws)) || (rc = grow(b->d_scenes, b->scenes_cap, (size_t)n)) ||
+        (rc = grow(b->d_items, b->items_cap, hitems.size())) ||
+        (rc = grow(b->d_blocks, b->blocks_cap, rblocks.size() + cblocks.size())))
+        return rc;
+    for (int i = 0; i < n; ++i) {
+        SceneDev &d = h[i];
+        char *base = b->d_ws + off[i];
+        d.srt = (int4 *)base;
+        base += ((sizeof(int4) * d.B) + 255) / 256 * 256;
+        d.part = (float2 *)base;
+        base += ((sizeof(float2) * (size_t)d.n_tiles * d.B) + 255) / 256 * 256;
+        d.rs = (float2 *)base;
+        base += ((sizeof(float2) * d.B) + 255) / 256 * 256;
+        d.gpart = (float2 *)base;
+    }
+    std::vector<int2> blocks(rblocks);
+    blocks.insert(blocks.end(), cblocks.begin(), cblocks.end());
+    hipStream_t st = (hipStream_t)stream;
+    // descriptors and lists are uploaded synchronously, ahead of any (captured) launch
+    if (hipMemcpy(b->d_scenes, h.data(), sizeof(SceneDev) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_items, hitems.data(), sizeof(int4) * hitems.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_blocks, blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(SPGM_E_DEVICE, "spgm_batch_solve: upload failed");
+    const void *ik[] = {(const void *)k_fwd_items<SPGM_PHASE_COMP32>, (const void *)k_fwd_items<SPGM_PHASE_F64>,
+                        (const void *)k_fwd_items<SPGM_PHASE_NAIVE32>, (const void *)k_adj_items<SPGM_PHASE_COMP32>,
+                        (const void *)k_adj_items<SPGM_PHASE_F64>, (const void *)k_adj_items<SPGM_PHASE_NAIVE32>};
+    for (const void *k : ik) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)k_sort_scenes, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(unsigned long long) * kSortChunk));
+    hipGetLastError();
+    // persistent grid: as many work-groups as fit on the chip at once
+    const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
+    const int n_items = (int)hitems.size();
+    const int grid_items = std::max(1, std::min(n_items, 256 * per_cu));
+    const int n_rb = (int)rblocks.size(), n_cb = (int)cblocks.size();
+    if (!use_graph) {
+        if ((rc = batch_launches(b, iters, n_items, grid_items, lds, max_chunks, p2, n_rb, n_cb, st))) return rc;
+        return ok();
+    }
+    if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(SPGM_E_DEVICE, "spgm_batch_solve: stream creation failed");
+    if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(SPGM_E_DEVICE, "spgm_batch_solve: capture failed to start");
+    rc = batch_launches(b, iters, n_items, grid_items, lds, max_chunks, p2, n_rb, n_cb, b->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || !g) return fail(SPGM_E_DEVICE, "spgm_batch_solve: capture failed");
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(SPGM_E_DEVICE, "spgm_batch_solve: graph instantiation failed");
+    }
+    const hipError_t le = hipGraphLaunch(ex, st);
+    hipGraphExecDestroy(ex);  // safe: destruction is deferred until the launch completes
+    hipGraphDestroy(g);
+    if (le != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_batch_solve: graph launch failed");
+    return ok();
+}
+
+int spgm_batch_status(spgm_batch *b, int32_t *status) {
+    if (!b || !status) return fail(SPGM_E_INVALID, "spgm_batch_status: batch and status must be non-NULL");
+    DeviceGuard guard(b->device);
+    int hval = 0;
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(&hval, b->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemset(b->d_status, 0, sizeof(int)) != hipSuccess)
+        return fail(SPGM_E_DEVICE, "spgm_batch_status: device error");
+    *status = hval ? SPGM_E_BADROW : SPGM_OK;
     return ok();
 }
 

@@ -48,6 +48,10 @@ CONFIGS = {
     "c4": dict(T=16, R=16, aperture=0.2, F=32, band=(20e9, 30e9), pulse=None,
                grid=(32, 32, 16), pitch=5e-3, z0=0.25, density=0.02, snr_db=25.0,
                B=2048, K=10, seed=1004),
+    # Ragged batch: 96 scenes, per scene T, R ~ U{8..32}, F ~ U{16..64}, k ~ U{1..4} with a
+    # (16k, 16k, 8k) grid at 3 mm, density ~ U[1 %, 5 %], B = ceil(M/4); see ragged_scenes().
+    "c3": dict(n_scenes=96, aperture=0.3, band=(20e9, 40e9), pitch=3e-3, z0=0.3, snr_db=25.0,
+               K=200, seed=1003),
     # Paper-shaped: 16 Tx + 9 Rx in 0.3 m, 11 f in 4-16 GHz, 61x61x21 voxels at 5 mm,
     # z0 = 0.5 m, structured minibatch (4, 4, 3).
     "P": dict(T=16, R=9, aperture=0.3, F=11, band=(4e9, 16e9), pulse=None,
@@ -175,3 +179,23 @@ def config_rows(name, K=None, B=None):
         nf, nt, nr = cfg["structured"]
         return draw_structured_rows(cfg["T"], cfg["R"], cfg["F"], nf, nt, nr, K, seed=cfg["seed"] + 3)
     return draw_rows(M, cfg["B"] if B is None else B, K, seed=cfg["seed"] + 3)
+
+
+def ragged_scenes(n=None, seed=None):
+    """Scenes of the ragged batch: list of dicts with geometry, scene, minibatch size B and seed."""
+    cfg = CONFIGS["c3"]
+    n = cfg["n_scenes"] if n is None else n
+    seed = cfg["seed"] if seed is None else seed
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        T, R = (int(v) for v in rng.integers(8, 33, size=2))
+        F = int(rng.integers(16, 65))
+        k = int(rng.integers(1, 5))
+        density = float(rng.uniform(0.01, 0.05))
+        sseed = seed * 1000 + i
+        geom = make_geometry(T, R, F, cfg["band"], (16 * k, 16 * k, 8 * k), cfg["pitch"], cfg["z0"], cfg["aperture"],
+                             seed=sseed)
+        M, N = dims(geom)
+        out.append(dict(geom=geom, density=density, snr_db=cfg["snr_db"], B=int(np.ceil(M / 4)), seed=sseed, M=M, N=N))
+    return out
