@@ -147,6 +147,51 @@ int spgm_unrolled_vjp_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, co
 int spgm_plan_autotune(spgm_plan *plan, int32_t B, const char *cache_path, int32_t *fwd_splits,
                        int32_t *adj_splits);
 
+/* Shared-geometry batches: K right-hand sides (K images of one scene geometry, or K
+ * measurement sets) through one set of entries of the minibatch.  Every entry of A_B is
+ * formed once per pass of up to 32 right-hand sides (compensated float32 phase as in
+ * SPGM_PHASE_COMP32), rounded to the chosen 16-bit type, and contracted with the right-hand
+ * sides, also rounded to that type, on the matrix cores with float32 accumulation.  K > 32 is
+ * processed in passes of 32.  Every reduction runs in a fixed order (bitwise reproducible).
+ * Expected relative error of each output column against exact arithmetic: about 1.6e-3
+ * (bfloat16) and 2e-4 (half), from the two roundings of each product.  Only plans created with
+ * SPGM_PHASE_COMP32 are supported (SPGM_E_UNSUPPORTED otherwise), and the brick tables must fit
+ * in LDS (min(T, R) <= 32 for the forward pass; SPGM_E_UNSUPPORTED otherwise). */
+typedef enum spgm_mm_precision {
+    /* bfloat16 operands (8 significant bits, float32 range) */
+    SPGM_MM_BF16 = 0,
+    /* IEEE half operands (11 significant bits); magnitudes of entries times 1, right-hand
+     * sides and scaled residuals must stay below 65504 */
+    SPGM_MM_FP16 = 1
+} spgm_mm_precision;
+
+/* Batched forward projection (Sec. II, Eq. 1 restricted to the minibatch, K images):
+ *     Y_d[j][k] = sum_n A_{rows_d[j], n} S_d[n][k],  j < B, k < K.
+ * S_d: complex64[N][K] (row-major, the K values of one voxel adjacent); Y_d: complex64[B][K]
+ * (output, caller row order).  1 <= B <= 2^24, K >= 1, precision a spgm_mm_precision.  May grow
+ * the plan's workspace (hipMalloc, synchronous). */
+int spgm_forward_batched(spgm_plan *plan, const int32_t *rows_d, int32_t B, int32_t K, const void *S_d,
+                         void *Y_d, int32_t precision, void *stream);
+
+/* Batched adjoint projection, unscaled:  G_d[n][k] = sum_j conj(A_{rows_d[j], n}) R_d[j][k].
+ * R_d: complex64[B][K] (caller row order); G_d: complex64[N][K] (output).  Limits as above. */
+int spgm_adjoint_batched(spgm_plan *plan, const int32_t *rows_d, int32_t B, int32_t K, const void *R_d,
+                         void *G_d, int32_t precision, void *stream);
+
+/* One SPGM iteration (Sec. IV, Eq. 5 with the gradient of Eq. 6) for each of K problems that
+ * share the geometry and the minibatch, in place:
+ *     S[:, k] <- S_alpha( S[:, k] - (eta/B) A_B^H (A_B S[:, k] - Ymeas[rows, k]) ).
+ * Ymeas_d: complex64[M][K] (full measurement vectors, column k for problem k); S_d:
+ * complex64[N][K] in/out.  eta > 0, alpha >= 0, finite.  Limits as above. */
+int spgm_step_batched(spgm_plan *plan, const int32_t *rows_d, int32_t B, int32_t K, const void *Ymeas_d,
+                      void *S_d, float eta, float alpha, int32_t precision, void *stream);
+
+/* `iters` batched SPGM iterations; iteration i uses rows_d[i*B .. i*B + B - 1].  Equivalent to
+ * `iters` calls of spgm_step_batched.  iters >= 0. */
+int spgm_solve_batched(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, int32_t K,
+                       const void *Ymeas_d, void *S_d, float eta, float alpha, int32_t precision,
+                       void *stream);
+
 /* Ragged batches of independent scenes (each with its own array, band and grid) advanced
  * together: every SPGM iteration of every scene is one launch per phase (sort, forward tile,
  * row reduction, adjoint tile, column reduction with the prox step).  The tile phases walk a

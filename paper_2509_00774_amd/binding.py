@@ -27,10 +27,14 @@ PHASE_COMP32 = 0
 PHASE_F64 = 1
 PHASE_NAIVE32 = 2
 
+MM_BF16 = 0
+MM_FP16 = 1
+
 EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
             "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
             "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph", "spgm_plan_autotune",
-            "spgm_batch_create", "spgm_batch_destroy", "spgm_batch_plan", "spgm_batch_solve", "spgm_batch_status")
+            "spgm_batch_create", "spgm_batch_destroy", "spgm_batch_plan", "spgm_batch_solve", "spgm_batch_status",
+            "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched")
 
 _dp = C.POINTER(C.c_double)
 
@@ -84,6 +88,10 @@ def load_library(path: str = LIB_PATH):
         "spgm_unrolled_vjp_step": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
         "spgm_plan_timing_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                   C.POINTER(C.c_int64)],
+        "spgm_forward_batched": [vp, vp, i32, i32, vp, vp, i32, vp],
+        "spgm_adjoint_batched": [vp, vp, i32, i32, vp, vp, i32, vp],
+        "spgm_step_batched": [vp, vp, i32, i32, vp, vp, f32, f32, i32, vp],
+        "spgm_solve_batched": [vp, vp, i32, i32, i32, vp, vp, f32, f32, i32, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -267,6 +275,65 @@ class Plan:
         fn, an = C.c_int64(), C.c_int64()
         _check(self._lib.spgm_plan_timing_read(self._h, C.byref(fm), C.byref(fn), C.byref(am), C.byref(an)))
         return fm.value, fn.value, am.value, an.value
+
+    # --- shared-geometry batches (K right-hand sides, 16-bit operands on the matrix cores) ---
+    @staticmethod
+    def _cols(t, rows_expected, name):
+        if t.dim() != 2 or t.shape[0] != rows_expected:
+            raise ValueError("%s must have shape (%d, K)" % (name, rows_expected))
+        return int(t.shape[1])
+
+    def spgm_forward_batched(self, rows, S, out=None, precision=MM_BF16, stream=None):
+        """Y = A_rows S for S of shape (N, K); returns Y of shape (B, K)."""
+        import torch
+        B = rows.numel()
+        K = self._cols(S, self.N, "S")
+        if out is None:
+            out = torch.empty(B, K, dtype=torch.complex64, device=S.device)
+        _check(self._lib.spgm_forward_batched(self._h, _dev(rows, torch.int32, "rows"), B, K,
+                                              _dev(S, torch.complex64, "S"),
+                                              _dev(out, torch.complex64, "out", B * K), int(precision),
+                                              _stream_ptr(stream)))
+        return out
+
+    def spgm_adjoint_batched(self, rows, R, out=None, precision=MM_BF16, stream=None):
+        """G = A_rows^H R for R of shape (B, K); returns G of shape (N, K)."""
+        import torch
+        B = rows.numel()
+        K = self._cols(R, B, "R")
+        if out is None:
+            out = torch.empty(self.N, K, dtype=torch.complex64, device=R.device)
+        _check(self._lib.spgm_adjoint_batched(self._h, _dev(rows, torch.int32, "rows"), B, K,
+                                              _dev(R, torch.complex64, "R"),
+                                              _dev(out, torch.complex64, "out", self.N * K), int(precision),
+                                              _stream_ptr(stream)))
+        return out
+
+    def spgm_step_batched(self, rows, Ymeas, S, eta, alpha, precision=MM_BF16, stream=None):
+        """One SPGM iteration of K problems in place: Ymeas (M, K), S (N, K)."""
+        import torch
+        K = self._cols(S, self.N, "S")
+        if self._cols(Ymeas, self.M, "Ymeas") != K:
+            raise ValueError("Ymeas and S must have the same number of columns")
+        _check(self._lib.spgm_step_batched(self._h, _dev(rows, torch.int32, "rows"), rows.numel(), K,
+                                           _dev(Ymeas, torch.complex64, "Ymeas"), _dev(S, torch.complex64, "S"),
+                                           float(eta), float(alpha), int(precision), _stream_ptr(stream)))
+        return S
+
+    def spgm_solve_batched(self, rows_table, Ymeas, S, eta, alpha, precision=MM_BF16, stream=None):
+        """``rows_table``: int32 tensor of shape (iters, B); Ymeas (M, K), S (N, K) in place."""
+        import torch
+        if rows_table.dim() != 2:
+            raise ValueError("rows_table must be 2-D (iters, B)")
+        iters, B = rows_table.shape
+        K = self._cols(S, self.N, "S")
+        if self._cols(Ymeas, self.M, "Ymeas") != K:
+            raise ValueError("Ymeas and S must have the same number of columns")
+        _check(self._lib.spgm_solve_batched(self._h, _dev(rows_table, torch.int32, "rows_table"), int(iters),
+                                            int(B), K, _dev(Ymeas, torch.complex64, "Ymeas"),
+                                            _dev(S, torch.complex64, "S"), float(eta), float(alpha),
+                                            int(precision), _stream_ptr(stream)))
+        return S
 
     # short aliases
     forward = spgm_forward

@@ -959,6 +959,8 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
     }
 }
 
+#include "spgm_mm.inc"
+
 // ------------------------------------------------------------------------------------------
 // Host side
 // ------------------------------------------------------------------------------------------
@@ -1035,6 +1037,13 @@ struct spgm_plan {
     size_t n_fwd = 0, n_adj = 0;
     // autotuned row splits per minibatch size: B -> (forward, adjoint)
     std::map<int, std::pair<int, int>> tuned;
+    // shared-geometry batches: packed right-hand sides [tile][z][8][2][64], forward partials
+    // [brick run][row][32], packed residuals [row/8][2][64], adjoint partials [split][voxel][32]
+    u32x4 *d_mm_s = nullptr;
+    float2 *d_mm_part = nullptr;
+    u32x4 *d_mm_r = nullptr;
+    float2 *d_mm_gpart = nullptr;
+    size_t mm_part_cap = 0, mm_r_cap = 0, mm_gpart_cap = 0;
 };
 
 // A batch of independent scenes (one plan each) advanced together.
@@ -1057,6 +1066,7 @@ struct spgm_batch {
 namespace {
 
 constexpr size_t kSolveSortRows = size_t(1) << 25;  // rows sorted ahead per solve batch (512 MiB)
+constexpr int kMaxLds = 160 * 1024;                   // LDS per work-group on gfx950
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
@@ -1235,6 +1245,191 @@ int ensure_vjp(spgm_plan *p) {
     return SPGM_OK;
 }
 
+
+// ---------------------------------------------------------------- shared-geometry batches
+template <typename T> int grow_buf(T *&ptr, size_t &cap, size_t need) {
+    if (need <= cap) return SPGM_OK;
+    hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    if (hipMalloc(&ptr, sizeof(T) * need) != hipSuccess)
+        return fail(SPGM_E_NOMEM, "spgm: batched workspace allocation failed (%zu bytes)", sizeof(T) * need);
+    cap = need;
+    return SPGM_OK;
+}
+
+// Forward launch shape: rows per wave 32 nrt (nrt = 1..4, fewer when LDS is short), work-groups
+// of 256 nrt rows, bricks grouped into runs so that about one work-group per compute unit is
+// launched (each run leaves one partial sum per row and right-hand side).
+struct MMFwdCfg {
+    int nrt = 1, rows_wg = 0, n_rb = 0, bpw = 1, n_super = 0;
+    size_t lds = 0;
+};
+
+MMFwdCfg mm_fwd_cfg(const spgm_plan *p, int B) {
+    MMFwdCfg c;
+    const int A = p->geo.T + p->geo.R;
+    c.nrt = std::min(4, std::max(1, (B + kWaves * kMMRows - 1) / (kWaves * kMMRows)));
+    while (c.nrt > 1 && mm_fwd_lds(c.nrt, A, p->geo.nL) > (size_t)kMaxLds) --c.nrt;
+    c.lds = mm_fwd_lds(c.nrt, A, p->geo.nL);
+    c.rows_wg = kWaves * kMMRows * c.nrt;
+    c.n_rb = (B + c.rows_wg - 1) / c.rows_wg;
+    c.bpw = std::max(1, (p->n_tiles * c.n_rb + 255) / 256);
+    c.n_super = (p->n_tiles + c.bpw - 1) / c.bpw;
+    return c;
+}
+
+// Adjoint launch shape: one work-group per (brick, row range); row ranges are multiples of 512
+// rows (four groups of 128-row rounds), split only when there are fewer than 256 bricks.
+struct MMAdjCfg {
+    int splits = 1, rpw = 0;
+    size_t lds = 0;
+};
+
+MMAdjCfg mm_adj_cfg(const spgm_plan *p, int B) {
+    MMAdjCfg c;
+    const int unit = kMMGroups * kMMStage;
+    int splits = std::max(1, (256 + p->n_tiles - 1) / p->n_tiles);
+    splits = std::min(splits, (B + unit - 1) / unit);
+    c.rpw = ((B + splits - 1) / splits + unit - 1) / unit * unit;
+    c.splits = (B + c.rpw - 1) / c.rpw;
+    c.lds = mm_adj_lds(p->geo.T + p->geo.R, p->geo.nL);
+    return c;
+}
+
+int mm_check(spgm_plan *p, const int32_t *rows, int B, int K, int prec, const char *who) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if (K < 1) return fail(SPGM_E_INVALID, "%s: K must be >= 1", who);
+    if (prec != SPGM_MM_BF16 && prec != SPGM_MM_FP16) return fail(SPGM_E_INVALID, "%s: unknown precision %d", who, prec);
+    if (p->phase_mode != SPGM_PHASE_COMP32)
+        return fail(SPGM_E_UNSUPPORTED, "%s: needs a plan created with SPGM_PHASE_COMP32", who);
+    if (mm_fwd_cfg(p, B).lds > (size_t)kMaxLds || mm_adj_cfg(p, B).lds > (size_t)kMaxLds)
+        return fail(SPGM_E_UNSUPPORTED, "%s: brick tables exceed LDS (smaller antenna array too large)", who);
+    return SPGM_OK;
+}
+
+int ensure_mm(spgm_plan *p, int B) {
+    int rc;
+    if ((rc = ensure_workspace(p, B))) return rc;  // sorted rows
+    const MMFwdCfg fc = mm_fwd_cfg(p, B);
+    const MMAdjCfg ac = mm_adj_cfg(p, B);
+    if (!p->d_mm_s && hipMalloc(&p->d_mm_s, sizeof(u32x4) * kMMSlice * kBZ * (size_t)p->n_tiles) != hipSuccess)
+        return fail(SPGM_E_NOMEM, "spgm: batched workspace allocation failed");
+    if ((rc = grow_buf(p->d_mm_part, p->mm_part_cap, (size_t)fc.n_super * B * kMMCols))) return rc;
+    if ((rc = grow_buf(p->d_mm_r, p->mm_r_cap, (size_t)((B + 7) / 8) * 2 * 64))) return rc;
+    if ((rc = grow_buf(p->d_mm_gpart, p->mm_gpart_cap, (size_t)ac.splits * p->N * kMMCols))) return rc;
+    return SPGM_OK;
+}
+
+// Forward pass of right-hand sides k0 .. k0+K-1 of S ([N][ld]) into the plan's partials.
+template <int PREC>
+int mm_forward_pass(spgm_plan *p, const MMFwdCfg &fc, const int4 *srt, int B, const float2 *S, int ld, int k0,
+                    int K, hipStream_t st) {
+    const size_t nth = (size_t)p->n_tiles * 2048;
+    k_mm_pack_s<PREC><<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(p->geo, S, ld, k0, K, p->n_tiles, p->d_mm_s);
+    int rc;
+    if ((rc = launch_check("batched pack"))) return rc;
+    hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
+    if (ev) hipEventRecord(ev[0], st);
+    const dim3 grid(fc.n_super, fc.n_rb);
+    switch (fc.nrt) {
+    case 1:
+        k_mm_fwd<PREC, 1><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, p->d_mm_s, p->d_mm_part);
+        break;
+    case 2:
+        k_mm_fwd<PREC, 2><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, p->d_mm_s, p->d_mm_part);
+        break;
+    case 3:
+        k_mm_fwd<PREC, 3><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, p->d_mm_s, p->d_mm_part);
+        break;
+    default:
+        k_mm_fwd<PREC, 4><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, p->d_mm_s, p->d_mm_part);
+    }
+    if (ev) hipEventRecord(ev[1], st);
+    return launch_check("batched forward");
+}
+
+template <int PREC>
+int mm_row_reduce(spgm_plan *p, const MMFwdCfg &fc, const int4 *srt, const int32_t *rows, int B, const float2 *y,
+                  int ldy, int k0, int K, float2 *out, int ldo, bool want_r, hipStream_t st) {
+    const int quads = ((B + 7) & ~7) / 4;
+    k_mm_row_reduce<PREC><<<(quads + 7) / 8, 256, 0, st>>>(p->geo, p->d_mm_part, fc.n_super, B, srt, rows, y, ldy, k0,
+                                                            K, out, ldo, want_r ? p->d_mm_r : nullptr);
+    return launch_check("batched row reduce");
+}
+
+template <int PREC>
+int mm_adjoint_pass(spgm_plan *p, const MMAdjCfg &ac, const int4 *srt, int B, hipStream_t st) {
+    hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
+    if (ev) hipEventRecord(ev[0], st);
+    k_mm_adj<PREC><<<dim3(p->n_tiles, ac.splits), kThreads, ac.lds, st>>>(p->geo, srt, B, ac.rpw, p->d_mm_r,
+                                                                         p->d_mm_gpart, (int)p->N);
+    if (ev) hipEventRecord(ev[1], st);
+    return launch_check("batched adjoint");
+}
+
+int mm_col_reduce(spgm_plan *p, const MMAdjCfg &ac, int k0, int K, int ld, float2 *g, float2 *s, float step,
+                  float alpha, hipStream_t st) {
+    const size_t nth = (size_t)p->N * kMMCols;
+    k_mm_col_reduce<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(p->d_mm_gpart, ac.splits, (int)p->N, k0, K, ld, g,
+                                                                   s, step, alpha);
+    return launch_check("batched column reduce");
+}
+
+// Y = A_B S over passes of 32 right-hand sides.
+template <int PREC>
+int mm_forward(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, int K, const float2 *S, float2 *Y,
+               hipStream_t st) {
+    const MMFwdCfg fc = mm_fwd_cfg(p, B);
+    int rc;
+    for (int k0 = 0; k0 < K; k0 += kMMCols) {
+        const int kc = std::min(kMMCols, K - k0);
+        if ((rc = mm_forward_pass<PREC>(p, fc, srt, B, S, K, k0, kc, st))) return rc;
+        if ((rc = mm_row_reduce<PREC>(p, fc, srt, rows, B, nullptr, 0, k0, kc, Y, K, false, st))) return rc;
+    }
+    return SPGM_OK;
+}
+
+// G = A_B^H R over passes of 32 right-hand sides.
+template <int PREC>
+int mm_adjoint(spgm_plan *p, const int4 *srt, int B, int K, const float2 *R, float2 *G, hipStream_t st) {
+    const MMAdjCfg ac = mm_adj_cfg(p, B);
+    int rc;
+    for (int k0 = 0; k0 < K; k0 += kMMCols) {
+        const int kc = std::min(kMMCols, K - k0);
+        const int quads = ((B + 7) & ~7) / 4;
+        k_mm_pack_r<PREC><<<(quads + 7) / 8, 256, 0, st>>>(p->geo, srt, B, R, K, k0, kc, p->d_mm_r);
+        if ((rc = launch_check("batched pack"))) return rc;
+        if ((rc = mm_adjoint_pass<PREC>(p, ac, srt, B, st))) return rc;
+        if ((rc = mm_col_reduce(p, ac, k0, kc, K, G, nullptr, 0.f, 0.f, st))) return rc;
+    }
+    return SPGM_OK;
+}
+
+// One batched SPGM iteration on sorted rows.
+template <int PREC>
+int mm_step(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, int K, const float2 *Ym, float2 *S, float eta,
+            float alpha, hipStream_t st) {
+    const MMFwdCfg fc = mm_fwd_cfg(p, B);
+    const MMAdjCfg ac = mm_adj_cfg(p, B);
+    int rc;
+    for (int k0 = 0; k0 < K; k0 += kMMCols) {
+        const int kc = std::min(kMMCols, K - k0);
+        if ((rc = mm_forward_pass<PREC>(p, fc, srt, B, S, K, k0, kc, st))) return rc;
+        if ((rc = mm_row_reduce<PREC>(p, fc, srt, rows, B, Ym, K, k0, kc, nullptr, 0, true, st))) return rc;
+        if ((rc = mm_adjoint_pass<PREC>(p, ac, srt, B, st))) return rc;
+        if ((rc = mm_col_reduce(p, ac, k0, kc, K, nullptr, S, eta / (float)B, alpha, st))) return rc;
+    }
+    return SPGM_OK;
+}
+
+int mm_step_any(spgm_plan *p, int prec, const int4 *srt, const int32_t *rows, int B, int K, const float2 *Ym,
+                float2 *S, float eta, float alpha, hipStream_t st) {
+    return prec == SPGM_MM_FP16 ? mm_step<SPGM_MM_FP16>(p, srt, rows, B, K, Ym, S, eta, alpha, st)
+                                : mm_step<SPGM_MM_BF16>(p, srt, rows, B, K, Ym, S, eta, alpha, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1356,7 +1551,7 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     const size_t A = (size_t)(T + R);
     p->lds_bytes = kAntBytes * A + kSub * (sizeof(float4) + sizeof(float2)) +
                    std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * kWaves);
-    if (p->lds_bytes > 160 * 1024) {
+    if (p->lds_bytes > (size_t)kMaxLds) {
         spgm_plan_destroy(p);
         return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: LDS footprint exceeds 160 KiB");
     }
@@ -1368,6 +1563,13 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
         (const void *)k_adj_tile<SPGM_PHASE_F64>, (const void *)k_adj_tile<SPGM_PHASE_NAIVE32>};
     for (const void *k : tile_kernels)
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
+    const void *mm_kernels[] = {
+        (const void *)k_mm_fwd<SPGM_MM_BF16, 1>, (const void *)k_mm_fwd<SPGM_MM_BF16, 2>,
+        (const void *)k_mm_fwd<SPGM_MM_BF16, 3>, (const void *)k_mm_fwd<SPGM_MM_BF16, 4>,
+        (const void *)k_mm_fwd<SPGM_MM_FP16, 1>, (const void *)k_mm_fwd<SPGM_MM_FP16, 2>,
+        (const void *)k_mm_fwd<SPGM_MM_FP16, 3>, (const void *)k_mm_fwd<SPGM_MM_FP16, 4>,
+        (const void *)k_mm_adj<SPGM_MM_BF16>, (const void *)k_mm_adj<SPGM_MM_FP16>};
+    for (const void *k : mm_kernels) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     hipGetLastError();
     *out = p;
     return ok();
@@ -1388,6 +1590,10 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_srt_all);
     hipFree(p->d_vjp);
     hipFree(p->d_vjp_part);
+    hipFree(p->d_mm_s);
+    hipFree(p->d_mm_part);
+    hipFree(p->d_mm_r);
+    hipFree(p->d_mm_gpart);
     drop_graph(p);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     for (hipEvent_t e : p->ev_fwd) hipEventDestroy(e);
@@ -2007,6 +2213,73 @@ int spgm_plan_timing_read(spgm_plan *p, double *fwd_ms, int64_t *fwd_n, double *
     if (fwd_n) *fwd_n = (int64_t)p->n_fwd;
     if (adj_n) *adj_n = (int64_t)p->n_adj;
     p->n_fwd = p->n_adj = 0;
+    return ok();
+}
+
+int spgm_forward_batched(spgm_plan *p, const int32_t *rows, int32_t B, int32_t K, const void *S, void *Y,
+                         int32_t prec, void *stream) {
+    int rc;
+    if ((rc = mm_check(p, rows, B, K, prec, "spgm_forward_batched"))) return rc;
+    if (!S || !Y) return fail(SPGM_E_INVALID, "spgm_forward_batched: S and Y must be non-NULL");
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_mm(p, B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    rc = prec == SPGM_MM_FP16
+             ? mm_forward<SPGM_MM_FP16>(p, p->d_srt, rows, B, K, (const float2 *)S, (float2 *)Y, st)
+             : mm_forward<SPGM_MM_BF16>(p, p->d_srt, rows, B, K, (const float2 *)S, (float2 *)Y, st);
+    return rc ? rc : ok();
+}
+
+int spgm_adjoint_batched(spgm_plan *p, const int32_t *rows, int32_t B, int32_t K, const void *R, void *G,
+                         int32_t prec, void *stream) {
+    int rc;
+    if ((rc = mm_check(p, rows, B, K, prec, "spgm_adjoint_batched"))) return rc;
+    if (!R || !G) return fail(SPGM_E_INVALID, "spgm_adjoint_batched: R and G must be non-NULL");
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_mm(p, B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    rc = prec == SPGM_MM_FP16 ? mm_adjoint<SPGM_MM_FP16>(p, p->d_srt, B, K, (const float2 *)R, (float2 *)G, st)
+                              : mm_adjoint<SPGM_MM_BF16>(p, p->d_srt, B, K, (const float2 *)R, (float2 *)G, st);
+    return rc ? rc : ok();
+}
+
+int spgm_step_batched(spgm_plan *p, const int32_t *rows, int32_t B, int32_t K, const void *Ym, void *S, float eta,
+                      float alpha, int32_t prec, void *stream) {
+    int rc;
+    if ((rc = mm_check(p, rows, B, K, prec, "spgm_step_batched"))) return rc;
+    if ((rc = check_step_args(Ym, S, eta, alpha))) return rc;
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_mm(p, B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    if ((rc = mm_step_any(p, prec, p->d_srt, rows, B, K, (const float2 *)Ym, (float2 *)S, eta, alpha, st))) return rc;
+    return ok();
+}
+
+int spgm_solve_batched(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, int32_t K, const void *Ym,
+                       void *S, float eta, float alpha, int32_t prec, void *stream) {
+    int rc;
+    if ((rc = mm_check(p, rows, B, K, prec, "spgm_solve_batched"))) return rc;
+    if ((rc = check_step_args(Ym, S, eta, alpha))) return rc;
+    if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve_batched: iters must be >= 0");
+    if (iters == 0) return ok();
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_mm(p, B))) return rc;
+    const int per = (int)std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
+    if ((rc = ensure_sorted_batch(p, (size_t)per * B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    for (int i0 = 0; i0 < iters; i0 += per) {
+        const int cnt = std::min(per, iters - i0);
+        const int32_t *ri = rows + (size_t)i0 * B;
+        if ((rc = run_sort(p, ri, B, cnt, p->d_srt_all, st))) return rc;
+        for (int i = 0; i < cnt; ++i) {
+            if ((rc = mm_step_any(p, prec, p->d_srt_all + (size_t)i * B, ri + (size_t)i * B, B, K, (const float2 *)Ym,
+                                  (float2 *)S, eta, alpha, st)))
+                return rc;
+        }
+    }
     return ok();
 }
 
