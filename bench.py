@@ -13,6 +13,8 @@ roofline of the dominant kernel (timed live with HIP events on the library's str
 the oracle's own rate on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--workload c1]
+       --workload c3     ragged batch of 96 scenes
+       --workload c1k32  32 scenes of the c1 geometry through the shared-geometry batched path
 """
 import argparse
 import hashlib
@@ -62,7 +64,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4", "c3"],
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4", "c3", "c1k32"],
                     help="c3 is the ragged batch of 96 scenes advanced together")
     ap.add_argument("--cpu-iters", type=int, default=5, help="iterations of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -98,6 +100,8 @@ def main():
     wl = args.workload
     if wl == "c3":
         return bench_ragged(args, torch, binding, dev)
+    if wl == "c1k32":
+        return bench_batched(args, torch, binding, dev)
     cfg = W.CONFIGS[wl]
     geom = W.config_geometry(wl)
     M, N = W.dims(geom)
@@ -316,6 +320,132 @@ def bench_ragged(args, torch, binding, dev):
     }
     print(json.dumps(out), flush=True)
     batch.close()
+
+
+# Dense bfloat16 MFMA peak of MI355X (matrix cores, no sparsity).
+MFMA_BF16_PEAK = 2.5e15
+# VALU slots per entry in the batched kernels: phase FMA, sin and cos (2 slots each), the two
+# amplitude multiplies and one packed conversion to 16 bits; the products move to the MFMA.
+MM_SLOTS_PER_ENTRY = 8
+
+
+def bench_batched(args, torch, binding, dev):
+    """Shared-geometry batch: 32 scenes of the c1 geometry advanced together by the batched
+    SPGM step (entries formed once per minibatch and applied to all 32 right-hand sides as a
+    bfloat16 complex GEMM on the matrix cores).  Also solves every scene with the float32
+    projector for the same iterations and reports both reconstruction errors (matched NMSE)."""
+    cfg = W.CONFIGS["c1"]
+    geom = W.config_geometry("c1")
+    M, N = W.dims(geom)
+    B = cfg["B"]
+    Kr = 32
+    steps, Wm = args.steps, args.warmup
+    prec = binding.MM_BF16
+    sj = json.load(open(STEP_SIZES))["c1"]
+    eta = float(np.float32(sj["eta"]))
+    alpha = float(np.float32(sj["lambda"] * eta))
+    log("batched c1 x %d scenes: M=%d N=%d B=%d; drawing %d minibatches" % (Kr, M, N, B, Wm + steps))
+    plan = binding.Plan(geom)
+    all_rows = torch.arange(M, dtype=torch.int32, device=dev)
+    S_true = np.zeros((N, Kr), dtype=np.complex64)
+    Y = np.zeros((M, Kr), dtype=np.complex64)
+    for k in range(Kr):
+        st, _ = W.random_scene(N, cfg["density"], seed=5000 + k)
+        S_true[:, k] = st
+        y0 = plan.spgm_forward(all_rows, torch.from_numpy(st.astype(np.complex64)).to(dev))
+        Y[:, k] = W.add_noise(y0.cpu().numpy().astype(np.complex128), cfg["snr_db"], seed=6000 + k)
+    Yd = torch.from_numpy(Y).to(dev)
+    rows = W.draw_rows(M, B, Wm + steps, seed=cfg["seed"] + 3)
+    rows_d = torch.from_numpy(rows).to(dev)
+    S = torch.zeros(N, Kr, dtype=torch.complex64, device=dev)
+    if Wm:
+        plan.spgm_solve_batched(rows_d[:Wm].contiguous(), Yd, S, eta, alpha, precision=prec)
+    S.zero_()
+    timed = rows_d[Wm:Wm + steps].contiguous()
+    plan.spgm_plan_timing(True)
+    plan.spgm_plan_timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.spgm_solve_batched(timed, Yd, S, eta, alpha, precision=prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwd_ms, fwd_n, adj_ms, adj_n = plan.spgm_plan_timing_read()
+    plan.spgm_plan_timing(False)
+    assert plan.spgm_plan_status() == 0
+    dt = t1 - t0
+    fwd_avg, adj_avg = fwd_ms / max(fwd_n, 1) * 1e-3, adj_ms / max(adj_n, 1) * 1e-3
+    entries = float(B) * N
+    log("timed %d batched iterations in %.3f s (%.3f ms each); batched forward %.4f ms, adjoint %.4f ms" % (
+        steps, dt, 1e3 * dt / steps, 1e3 * fwd_avg, 1e3 * adj_avg))
+    # Matched reconstruction error: the float32 projector on each scene, same rows and steps.
+    S_b = S.cpu().numpy().astype(np.complex128)
+    nmse_b, nmse_f = [], []
+    t_f = 0.0
+    for k in range(Kr):
+        s32 = torch.zeros(N, dtype=torch.complex64, device=dev)
+        yk = Yd[:, k].contiguous()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        plan.spgm_solve(timed, yk, s32, eta, alpha)
+        torch.cuda.synchronize()
+        t_f += time.perf_counter() - a
+        st = S_true[:, k].astype(np.complex128)
+        den = np.sum(np.abs(st) ** 2)
+        nmse_b.append(10 * np.log10(np.sum(np.abs(S_b[:, k] - st) ** 2) / den))
+        nmse_f.append(10 * np.log10(np.sum(np.abs(s32.cpu().numpy() - st) ** 2) / den))
+    dnmse = float(np.max(np.abs(np.array(nmse_b) - np.array(nmse_f))))
+    log("NMSE vs truth after %d iterations: batched bf16 mean %.3f dB, float32 mean %.3f dB, worst gap %.4f dB; "
+        "float32 solves of the %d scenes one by one: %.3f s" % (steps, np.mean(nmse_b), np.mean(nmse_f), dnmse, Kr, t_f))
+    flops = 8.0 * entries * Kr  # real flops of one batched operator
+    kname, kavg = ("k_mm_fwd", fwd_avg) if fwd_avg >= adj_avg else ("k_mm_adj", adj_avg)
+    achieved = flops / kavg
+    cpu = None
+    rel = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.Oracle(geom)
+        y1 = Y[:, 0].astype(np.complex128)
+        s_par = torch.zeros(N, 1, dtype=torch.complex64, device=dev)
+        plan.spgm_solve_batched(rows_d[:1].contiguous(), Yd[:, :1].contiguous(), s_par, eta, alpha, precision=prec)
+        log("oracle: one SPGM iteration of scene 0 on %d threads" % oracle.num_threads())
+        c0 = time.perf_counter()
+        ref = orc.solve(rows[:1], y1, np.zeros(N), eta, alpha)
+        c1 = time.perf_counter()
+        rel = oracle.rel_l2(s_par.cpu().numpy()[:, 0], ref)
+        cpu = {"value": round(entries / (c1 - c0) / 1e9, 4), "unit": "G entry-RHS products/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "1 SPGM iteration of 1 of the 32 scenes (B=%d x N=%d), FP64, %.1f s" % (B, N, c1 - c0)}
+        log("oracle: %.1f s; batched bf16 iterate after 1 iteration rel_l2 vs oracle %.3e" % (c1 - c0, rel))
+    out = {
+        "metric": "batched projector G entry-RHS products/s (K x B x N per operator, forward + adjoint) at matched NMSE",
+        "value": round(entries * Kr * steps / dt / 1e9, 1),
+        "unit": "G entry-RHS/s",
+        "n_gpus": 1, "steps": steps, "warmup": Wm, "ms_per_step": round(1e3 * dt / steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "c1 geometry (32 Tx + 32 Rx, 64 frequencies, 64x64x32 voxels, B=4096) with K=32 "
+                               "scenes sharing the minibatch; batched SPGM step, bfloat16 operands, float32 accumulation",
+                   "M": M, "N": N, "B": B, "K": Kr},
+        "spgm_iters_per_s": round(steps / dt, 2),
+        "scene_iters_per_s": round(Kr * steps / dt, 1),
+        "float32_scene_iters_per_s": round(Kr * steps / t_f, 1),
+        "nmse_db_batched_mean": round(float(np.mean(nmse_b)), 4),
+        "nmse_db_float32_mean": round(float(np.mean(nmse_f)), 4),
+        "nmse_db_worst_gap": round(dnmse, 4),
+        "rel_l2_vs_oracle_after_1_iter": None if rel is None else float("%.3e" % rel),
+        "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved / 1e12, 2),
+                     "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK, 4),
+                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": round(kavg * 1e3, 5),
+                     "fwd_mm_ms": round(fwd_avg * 1e3, 5), "adj_mm_ms": round(adj_avg * 1e3, 5),
+                     "fwd_gentries_per_s": round(entries / fwd_avg / 1e9, 1),
+                     "adj_gentries_per_s": round(entries / adj_avg / 1e9, 1),
+                     "alu_view": {"achieved": round(entries * MM_SLOTS_PER_ENTRY / kavg / 1e12, 3),
+                                  "peak": round(VALU_SLOTS_PER_S / 1e12, 3), "unit": "T VALU lane-slots/s",
+                                  "frac": round(entries * MM_SLOTS_PER_ENTRY / kavg / VALU_SLOTS_PER_S, 4),
+                                  "slots_per_entry": MM_SLOTS_PER_ENTRY}},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
 
 
 if __name__ == "__main__":
