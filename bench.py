@@ -37,7 +37,9 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 SLOTS_PER_ENTRY = 9
 STEP_SIZES = os.path.join(ROOT, "tests", "golden", "step_sizes.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
-SOURCE = os.path.join(ROOT, "paper_2509_00774_amd", "csrc", "spgm.hip")
+SOURCES = [os.path.join(ROOT, "paper_2509_00774_amd", "csrc", "spgm.hip"),
+           os.path.join(ROOT, "paper_2509_00774_amd", "csrc", "spgm_mm.inc"),
+           os.path.join(ROOT, "include", "spgm.h")]
 
 
 def log(*a):
@@ -45,7 +47,11 @@ def log(*a):
 
 
 def source_sha():
-    return hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()[:16]
+    """Fingerprint of every source of libspgm.so (counter records are void once any changes)."""
+    h = hashlib.sha256()
+    for path in SOURCES:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(kernel, workload):
