@@ -192,6 +192,39 @@ int spgm_solve_batched(spgm_plan *plan, const int32_t *rows_d, int32_t iters, in
                        const void *Ymeas_d, void *S_d, float eta, float alpha, int32_t precision,
                        void *stream);
 
+/* Structured minibatches (the Cartesian-product minibatches of Sec. IV-A and Sec. V): a
+ * frequency subset f_idx (nf entries), a transmitter subset t_idx (nt) and a receiver subset
+ * r_idx (nr), device int32 arrays; the minibatch holds the B = nf*nt*nr rows
+ *     j = (i*nt + a)*nr + b  ->  m = (f_idx[i]*T + t_idx[a])*R + r_idx[b].
+ * Eq. 2 factors over the two antennas of a row, A_{(f,t,r),n} = q_f a_T[f,t,n] a_R[f,r,n] with
+ * a_X = exp(-j 2 pi f d_X / c) / d_X and q_f = p(f)/(4 pi), so only nf*(nt+nr)*N factors are formed
+ * (compensated float32 phase per antenna) and the per-frequency products run as float32 GEMMs
+ * on the matrix cores; results keep float32 accuracy (same tolerance as spgm_forward).
+ * 1 <= nt, nr <= 32, 1 <= nf <= 65535, B <= 2^24; indices need not be distinct.  An index outside its
+ * range sets the plan's sticky status (SPGM_E_BADROW, read by spgm_plan_status) and is replaced
+ * by 0.  Only SPGM_PHASE_COMP32 plans are supported (SPGM_E_UNSUPPORTED otherwise).  May grow
+ * the plan's workspace (hipMalloc, synchronous). */
+
+/* y_d[j] = sum_n A_{m_j, n} s_d[n]; s_d: complex64[N]; y_d: complex64[B] (minibatch order). */
+int spgm_forward_structured(spgm_plan *plan, const int32_t *f_idx_d, int32_t nf, const int32_t *t_idx_d,
+                            int32_t nt, const int32_t *r_idx_d, int32_t nr, const void *s_d, void *y_d,
+                            void *stream);
+
+/* g_d[n] = sum_j conj(A_{m_j, n}) r_d[j], unscaled; r_d: complex64[B]; g_d: complex64[N]. */
+int spgm_adjoint_structured(spgm_plan *plan, const int32_t *f_idx_d, int32_t nf, const int32_t *t_idx_d,
+                            int32_t nt, const int32_t *r_idx_d, int32_t nr, const void *r_d, void *g_d,
+                            void *stream);
+
+/* One SPGM iteration (as spgm_step) on the structured minibatch; y_d: complex64[M]. */
+int spgm_step_structured(spgm_plan *plan, const int32_t *f_idx_d, int32_t nf, const int32_t *t_idx_d,
+                         int32_t nt, const int32_t *r_idx_d, int32_t nr, const void *y_d, void *s_d,
+                         float eta, float alpha, void *stream);
+
+/* `iters` iterations; iteration k uses f_idx_d[k*nf ..], t_idx_d[k*nt ..], r_idx_d[k*nr ..]. */
+int spgm_solve_structured(spgm_plan *plan, const int32_t *f_idx_d, int32_t nf, const int32_t *t_idx_d,
+                          int32_t nt, const int32_t *r_idx_d, int32_t nr, int32_t iters, const void *y_d,
+                          void *s_d, float eta, float alpha, void *stream);
+
 /* Ragged batches of independent scenes (each with its own array, band and grid) advanced
  * together: every SPGM iteration of every scene is one launch per phase (sort, forward tile,
  * row reduction, adjoint tile, column reduction with the prox step).  The tile phases walk a

@@ -34,7 +34,8 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
             "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph", "spgm_plan_autotune",
             "spgm_batch_create", "spgm_batch_destroy", "spgm_batch_plan", "spgm_batch_solve", "spgm_batch_status",
-            "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched")
+            "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched",
+            "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured")
 
 _dp = C.POINTER(C.c_double)
 
@@ -92,6 +93,10 @@ def load_library(path: str = LIB_PATH):
         "spgm_adjoint_batched": [vp, vp, i32, i32, vp, vp, i32, vp],
         "spgm_step_batched": [vp, vp, i32, i32, vp, vp, f32, f32, i32, vp],
         "spgm_solve_batched": [vp, vp, i32, i32, i32, vp, vp, f32, f32, i32, vp],
+        "spgm_forward_structured": [vp, vp, i32, vp, i32, vp, i32, vp, vp, vp],
+        "spgm_adjoint_structured": [vp, vp, i32, vp, i32, vp, i32, vp, vp, vp],
+        "spgm_step_structured": [vp, vp, i32, vp, i32, vp, i32, vp, vp, f32, f32, vp],
+        "spgm_solve_structured": [vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, f32, f32, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -334,6 +339,54 @@ class Plan:
                                             _dev(S, torch.complex64, "S"), float(eta), float(alpha),
                                             int(precision), _stream_ptr(stream)))
         return S
+
+    # --- structured minibatches (frequency x Tx x Rx subsets, separable factorisation) --------
+    @staticmethod
+    def _subsets(fs, ts, rs):
+        import torch
+        return [(_dev(x, torch.int32, name), int(x.shape[-1])) for x, name in ((fs, "f_idx"), (ts, "t_idx"),
+                                                                              (rs, "r_idx"))]
+
+    def spgm_forward_structured(self, fs, ts, rs, s, out=None, stream=None):
+        """y = A_rows s for the rows of fs x ts x rs (order (i, a, b)); returns complex64[nf*nt*nr]."""
+        import torch
+        (f, nf), (t, nt), (r, nr) = self._subsets(fs, ts, rs)
+        B = nf * nt * nr
+        if out is None:
+            out = torch.empty(B, dtype=torch.complex64, device=s.device)
+        _check(self._lib.spgm_forward_structured(self._h, f, nf, t, nt, r, nr, _dev(s, torch.complex64, "s", self.N),
+                                                 _dev(out, torch.complex64, "out", B), _stream_ptr(stream)))
+        return out
+
+    def spgm_adjoint_structured(self, fs, ts, rs, r_vec, out=None, stream=None):
+        import torch
+        (f, nf), (t, nt), (r, nr) = self._subsets(fs, ts, rs)
+        B = nf * nt * nr
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.complex64, device=r_vec.device)
+        _check(self._lib.spgm_adjoint_structured(self._h, f, nf, t, nt, r, nr, _dev(r_vec, torch.complex64, "r", B),
+                                                 _dev(out, torch.complex64, "out", self.N), _stream_ptr(stream)))
+        return out
+
+    def spgm_step_structured(self, fs, ts, rs, y, s, eta, alpha, stream=None):
+        import torch
+        (f, nf), (t, nt), (r, nr) = self._subsets(fs, ts, rs)
+        _check(self._lib.spgm_step_structured(self._h, f, nf, t, nt, r, nr, _dev(y, torch.complex64, "y", self.M),
+                                              _dev(s, torch.complex64, "s", self.N), float(eta), float(alpha),
+                                              _stream_ptr(stream)))
+        return s
+
+    def spgm_solve_structured(self, fs, ts, rs, y, s, eta, alpha, stream=None):
+        """fs (iters, nf), ts (iters, nt), rs (iters, nr) int32 tensors."""
+        import torch
+        if fs.dim() != 2 or ts.dim() != 2 or rs.dim() != 2 or not (fs.shape[0] == ts.shape[0] == rs.shape[0]):
+            raise ValueError("fs, ts, rs must be 2-D with the same number of iterations")
+        (f, nf), (t, nt), (r, nr) = self._subsets(fs, ts, rs)
+        _check(self._lib.spgm_solve_structured(self._h, f, nf, t, nt, r, nr, int(fs.shape[0]),
+                                               _dev(y, torch.complex64, "y", self.M),
+                                               _dev(s, torch.complex64, "s", self.N), float(eta), float(alpha),
+                                               _stream_ptr(stream)))
+        return s
 
     # short aliases
     forward = spgm_forward

@@ -960,6 +960,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 }
 
 #include "spgm_mm.inc"
+#include "spgm_sf.inc"
 
 // ------------------------------------------------------------------------------------------
 // Host side
@@ -1044,6 +1045,9 @@ struct spgm_plan {
     u32x4 *d_mm_r = nullptr;
     float2 *d_mm_gpart = nullptr;
     size_t mm_part_cap = 0, mm_r_cap = 0, mm_gpart_cap = 0;
+    // structured minibatches: measurement index of every row of the current minibatch
+    int32_t *d_sf_rows = nullptr;
+    size_t sf_rows_cap = 0;
 };
 
 // A batch of independent scenes (one plan each) advanced together.
@@ -1430,6 +1434,65 @@ int mm_step_any(spgm_plan *p, int prec, const int4 *srt, const int32_t *rows, in
                                 : mm_step<SPGM_MM_BF16>(p, srt, rows, B, K, Ym, S, eta, alpha, st);
 }
 
+// ---------------------------------------------------------------- structured minibatches
+struct SFArgs {
+    const int32_t *fi, *ti, *ri;
+    int nf, nt, nr, B;
+};
+
+int sf_check(spgm_plan *p, const SFArgs &a, const char *who) {
+    if (!p) return fail(SPGM_E_INVALID, "%s: plan is NULL", who);
+    if (!a.fi || !a.ti || !a.ri) return fail(SPGM_E_INVALID, "%s: index arrays must be non-NULL", who);
+    if (a.nf < 1 || a.nf > 65535 || a.nt < 1 || a.nr < 1 || a.nt > kSFMax || a.nr > kSFMax)
+        return fail(SPGM_E_INVALID, "%s: need 1 <= nf <= 65535 and 1 <= nt, nr <= %d", who, kSFMax);
+    if ((int64_t)a.nf * a.nt * a.nr > kMaxB) return fail(SPGM_E_INVALID, "%s: nf*nt*nr exceeds %d", who, kMaxB);
+    if (p->phase_mode != SPGM_PHASE_COMP32)
+        return fail(SPGM_E_UNSUPPORTED, "%s: needs a plan created with SPGM_PHASE_COMP32", who);
+    if (sf_lds_bytes(p->geo.T + p->geo.R) > (size_t)kMaxLds)
+        return fail(SPGM_E_UNSUPPORTED, "%s: antenna tables exceed LDS", who);
+    return SPGM_OK;
+}
+
+// Workspace and the row table of a structured minibatch (sorted-row format, natural order).
+int sf_prepare(spgm_plan *p, const SFArgs &a, hipStream_t st) {
+    int rc;
+    if ((rc = ensure_workspace(p, a.B))) return rc;
+    if ((rc = grow_buf(p->d_sf_rows, p->sf_rows_cap, (size_t)a.B))) return rc;
+    k_sf_rows<<<(a.B + 255) / 256, 256, 0, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr, p->d_srt, p->d_sf_rows,
+                                                  p->d_status);
+    return launch_check("structured rows");
+}
+
+int sf_forward_partials(spgm_plan *p, const SFArgs &a, const float2 *s, hipStream_t st) {
+    hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
+    if (ev) hipEventRecord(ev[0], st);
+    k_sf_fwd<<<p->n_tiles, kThreads, sf_lds_bytes(p->geo.T + p->geo.R), st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri,
+                                                                              a.nr, s, p->d_part, a.B);
+    if (ev) hipEventRecord(ev[1], st);
+    return launch_check("structured forward");
+}
+
+// Adjoint of the scaled residuals in p->d_rs into p->d_gpart[0].
+int sf_adjoint_partials(spgm_plan *p, const SFArgs &a, hipStream_t st) {
+    hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
+    if (ev) hipEventRecord(ev[0], st);
+    k_sf_adj<<<p->n_tiles, kThreads, sf_lds_bytes(p->geo.T + p->geo.R), st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri,
+                                                                              a.nr, p->d_rs, p->d_gpart, (int)p->N);
+    if (ev) hipEventRecord(ev[1], st);
+    return launch_check("structured adjoint");
+}
+
+int sf_step(spgm_plan *p, const SFArgs &a, const float2 *y, float2 *s, float eta, float alpha, hipStream_t st) {
+    int rc;
+    if ((rc = sf_prepare(p, a, st))) return rc;
+    if ((rc = sf_forward_partials(p, a, s, st))) return rc;
+    if ((rc = run_row_reduce(p, p->d_srt, p->d_sf_rows, a.B, y, nullptr, p->d_rs, st))) return rc;
+    if ((rc = sf_adjoint_partials(p, a, st))) return rc;
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, 1, (int)p->N, nullptr, s, eta / (float)a.B,
+                                                             alpha);
+    return launch_check("column reduce");
+}
+
 }  // namespace
 
 extern "C" {
@@ -1570,6 +1633,8 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
         (const void *)k_mm_fwd<SPGM_MM_FP16, 3>, (const void *)k_mm_fwd<SPGM_MM_FP16, 4>,
         (const void *)k_mm_adj<SPGM_MM_BF16>, (const void *)k_mm_adj<SPGM_MM_FP16>};
     for (const void *k : mm_kernels) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    hipFuncSetAttribute((const void *)k_sf_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
+    hipFuncSetAttribute((const void *)k_sf_adj, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
     hipGetLastError();
     *out = p;
     return ok();
@@ -1594,6 +1659,7 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_mm_part);
     hipFree(p->d_mm_r);
     hipFree(p->d_mm_gpart);
+    hipFree(p->d_sf_rows);
     drop_graph(p);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     for (hipEvent_t e : p->ev_fwd) hipEventDestroy(e);
@@ -2279,6 +2345,65 @@ int spgm_solve_batched(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t
                                   (float2 *)S, eta, alpha, st)))
                 return rc;
         }
+    }
+    return ok();
+}
+
+int spgm_forward_structured(spgm_plan *p, const int32_t *f_idx, int32_t nf, const int32_t *t_idx, int32_t nt,
+                            const int32_t *r_idx, int32_t nr, const void *s, void *y, void *stream) {
+    const SFArgs a{f_idx, t_idx, r_idx, nf, nt, nr, nf * nt * nr};
+    int rc;
+    if ((rc = sf_check(p, a, "spgm_forward_structured"))) return rc;
+    if (!s || !y) return fail(SPGM_E_INVALID, "spgm_forward_structured: s and y must be non-NULL");
+    DeviceGuard guard(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = sf_prepare(p, a, st))) return rc;
+    if ((rc = sf_forward_partials(p, a, (const float2 *)s, st))) return rc;
+    if ((rc = run_row_reduce(p, p->d_srt, p->d_sf_rows, a.B, nullptr, (float2 *)y, nullptr, st))) return rc;
+    return ok();
+}
+
+int spgm_adjoint_structured(spgm_plan *p, const int32_t *f_idx, int32_t nf, const int32_t *t_idx, int32_t nt,
+                            const int32_t *r_idx, int32_t nr, const void *r, void *g, void *stream) {
+    const SFArgs a{f_idx, t_idx, r_idx, nf, nt, nr, nf * nt * nr};
+    int rc;
+    if ((rc = sf_check(p, a, "spgm_adjoint_structured"))) return rc;
+    if (!r || !g) return fail(SPGM_E_INVALID, "spgm_adjoint_structured: r and g must be non-NULL");
+    DeviceGuard guard(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = sf_prepare(p, a, st))) return rc;
+    k_gather_scale<<<(a.B + 255) / 256, 256, 0, st>>>(p->geo, p->d_srt, a.B, (const float2 *)r, p->d_rs);
+    if ((rc = launch_check("gather"))) return rc;
+    if ((rc = sf_adjoint_partials(p, a, st))) return rc;
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, 1, (int)p->N, (float2 *)g, nullptr, 0.f, 0.f);
+    if ((rc = launch_check("column reduce"))) return rc;
+    return ok();
+}
+
+int spgm_step_structured(spgm_plan *p, const int32_t *f_idx, int32_t nf, const int32_t *t_idx, int32_t nt,
+                         const int32_t *r_idx, int32_t nr, const void *y, void *s, float eta, float alpha,
+                         void *stream) {
+    const SFArgs a{f_idx, t_idx, r_idx, nf, nt, nr, nf * nt * nr};
+    int rc;
+    if ((rc = sf_check(p, a, "spgm_step_structured"))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    DeviceGuard guard(p->device);
+    if ((rc = sf_step(p, a, (const float2 *)y, (float2 *)s, eta, alpha, (hipStream_t)stream))) return rc;
+    return ok();
+}
+
+int spgm_solve_structured(spgm_plan *p, const int32_t *f_idx, int32_t nf, const int32_t *t_idx, int32_t nt,
+                          const int32_t *r_idx, int32_t nr, int32_t iters, const void *y, void *s, float eta,
+                          float alpha, void *stream) {
+    const SFArgs a0{f_idx, t_idx, r_idx, nf, nt, nr, nf * nt * nr};
+    int rc;
+    if ((rc = sf_check(p, a0, "spgm_solve_structured"))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve_structured: iters must be >= 0");
+    DeviceGuard guard(p->device);
+    for (int k = 0; k < iters; ++k) {
+        const SFArgs a{f_idx + (size_t)k * nf, t_idx + (size_t)k * nt, r_idx + (size_t)k * nr, nf, nt, nr, a0.B};
+        if ((rc = sf_step(p, a, (const float2 *)y, (float2 *)s, eta, alpha, (hipStream_t)stream))) return rc;
     }
     return ok();
 }

@@ -137,17 +137,32 @@ def draw_rows(M, B, K, seed=0):
     return out
 
 
+def draw_structured_subsets(T, R, F, nf, nt, nr, K, seed=0):
+    """K structured minibatches as subsets: (fs [K][nf], ts [K][nt], rs [K][nr]) int32, each drawn
+    without replacement (frequencies, then transmitters, then receivers per minibatch)."""
+    rng = np.random.default_rng(seed)
+    fs = np.empty((K, nf), dtype=np.int32)
+    ts = np.empty((K, nt), dtype=np.int32)
+    rs = np.empty((K, nr), dtype=np.int32)
+    for k in range(K):
+        fs[k] = rng.choice(F, size=nf, replace=False)
+        ts[k] = rng.choice(T, size=nt, replace=False)
+        rs[k] = rng.choice(R, size=nr, replace=False)
+    return fs, ts, rs
+
+
+def structured_rows(T, R, fs, ts, rs):
+    """Rows of the Cartesian product in minibatch order j = (i nt + a) nr + b:
+    m = (fs[i] T + ts[a]) R + rs[b]."""
+    fs, ts, rs = (np.asarray(x, dtype=np.int64) for x in (fs, ts, rs))
+    return ((fs[:, None, None] * T + ts[None, :, None]) * R + rs[None, None, :]).reshape(-1).astype(np.int32)
+
+
 def draw_structured_rows(T, R, F, nf, nt, nr, K, seed=0):
     """K x (nf*nt*nr) table of Cartesian-product minibatches: nf frequencies, nt Tx and nr Rx
     drawn without replacement; row index m = (i_f*T + i_t)*R + i_r."""
-    rng = np.random.default_rng(seed)
-    out = np.empty((K, nf * nt * nr), dtype=np.int32)
-    for k in range(K):
-        fs = rng.choice(F, size=nf, replace=False)
-        ts = rng.choice(T, size=nt, replace=False)
-        rs = rng.choice(R, size=nr, replace=False)
-        out[k] = ((fs[:, None, None] * T + ts[None, :, None]) * R + rs[None, None, :]).reshape(-1)
-    return out
+    fs, ts, rs = draw_structured_subsets(T, R, F, nf, nt, nr, K, seed=seed)
+    return np.stack([structured_rows(T, R, fs[k], ts[k], rs[k]) for k in range(K)])
 
 
 def random_complex(n, seed=0, dtype=np.complex128):
