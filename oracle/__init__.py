@@ -15,6 +15,9 @@ Functions and the passage each one follows:
 * :meth:`Oracle.step`, :meth:`Oracle.solve`              -- SPGM / PGM iteration (Sec. IV, Eq. 5)
 * :meth:`Oracle.lambda_max`                              -- smallest lambda with zero minimiser of Eq. 3 with Eq. 4
 * :meth:`Oracle.lipschitz`                               -- power iteration on A_B^H A_B / B (step-size choice)
+* :func:`prox_elastic`, :func:`prox_tv_magnitude`,
+  :func:`grad3`, :func:`grad3_adjoint`, :meth:`Oracle.step_reg` -- other regularisers in place of the l1 prox
+                                                            (Sec. III notes the extension; readings in spgm_oracle.c)
 * :func:`nmse`, :func:`psnr_magnitude`                   -- error metrics (Sec. V, PSNR over normalised magnitudes)
 * :func:`unrolled_forward`, :func:`unrolled_vjp`         -- K iterations of Eq. 5 with per-iteration step size
                                                             and threshold, and their chain-rule gradient
@@ -65,6 +68,12 @@ def _lib():
             "ora_stochastic_gradient": (None, [g, _ip, C.c_int32, _dp, _dp, _dp]),
             "ora_step": (None, [g, _ip, C.c_int32, _dp, _dp, C.c_double, C.c_double]),
             "ora_solve": (None, [g, _ip, C.c_int32, C.c_int32, _dp, _dp, C.c_double, C.c_double]),
+            "ora_grad3": (None, [C.c_int32, C.c_int32, C.c_int32, _dp, _dp]),
+            "ora_grad3_adjoint": (None, [C.c_int32, C.c_int32, C.c_int32, _dp, _dp]),
+            "ora_prox_elastic": (None, [_dp, C.c_int64, C.c_double, C.c_double]),
+            "ora_prox_tv_magnitude": (None, [_dp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]),
+            "ora_step_reg": (None, [g, _ip, C.c_int32, _dp, _dp, C.c_double, C.c_double, C.c_int32,
+                                    C.c_double, C.c_int32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -191,6 +200,16 @@ class Oracle:
         _lib().ora_step(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(y), _ptr(s), float(eta), float(alpha))
         return s
 
+    def step_reg(self, rows, y, s, eta: float, alpha: float, kind: int, mu: float = 0.0,
+                 tv_iters: int = 0) -> np.ndarray:
+        """Eq. 5 with the prox of another regulariser: kind 0 = l1, 1 = elastic net, 2 = magnitude TV."""
+        rows, y = _i32(rows), _c128(y).reshape(-1)
+        s = _c128(s).reshape(-1).copy()
+        assert y.size == self.M and s.size == self.N
+        _lib().ora_step_reg(C.byref(self._g), _ptr(rows, _ip), rows.size, _ptr(y), _ptr(s), float(eta),
+                            float(alpha), int(kind), float(mu), int(tv_iters))
+        return s
+
     def solve(self, rows_table, y, s0, eta: float, alpha: float) -> np.ndarray:
         """K iterations; ``rows_table`` is K x B (iteration k uses row k)."""
         rows = _i32(rows_table)
@@ -224,6 +243,45 @@ def prox_l1(v, alpha: float) -> np.ndarray:
     v = _c128(v).reshape(-1).copy()
     _lib().ora_prox_l1(_ptr(v), v.size, float(alpha))
     return v
+
+
+def prox_elastic(v, alpha: float, mu: float) -> np.ndarray:
+    """Prox of alpha*(||.||_1 + (mu/2)||.||^2): S_alpha(v) / (1 + alpha mu)."""
+    v = _c128(v).reshape(-1).copy()
+    _lib().ora_prox_elastic(_ptr(v), v.size, float(alpha), float(mu))
+    return v
+
+
+def grad3(u, grid) -> np.ndarray:
+    """Forward differences of a real (nz, ny, nx) volume, shape (3, N); zero on each upper face."""
+    nx, ny, nz = (int(v) for v in grid)
+    u = _f64(u).reshape(-1)
+    assert u.size == nx * ny * nz
+    w = np.zeros(3 * u.size)
+    _lib().ora_grad3(nx, ny, nz, _ptr(u), _ptr(w))
+    return w.reshape(3, -1)
+
+
+def grad3_adjoint(w, grid) -> np.ndarray:
+    """Adjoint of :func:`grad3` (minus the divergence), shape (N,)."""
+    nx, ny, nz = (int(v) for v in grid)
+    w = _f64(w).reshape(-1)
+    assert w.size == 3 * nx * ny * nz
+    out = np.zeros(nx * ny * nz)
+    _lib().ora_grad3_adjoint(nx, ny, nz, _ptr(w), _ptr(out))
+    return out
+
+
+def prox_tv_magnitude(v, grid, alpha: float, iters: int, return_dual: bool = False):
+    """Prox of alpha*TV(|.|) with the phase kept; ``iters`` dual fast-gradient-projection iterations.
+
+    With ``return_dual`` also returns the final dual field w, shape (3, N)."""
+    nx, ny, nz = (int(x) for x in grid)
+    v = _c128(v).reshape(-1).copy()
+    assert v.size == nx * ny * nz
+    w = np.zeros(3 * v.size)
+    _lib().ora_prox_tv_magnitude(_ptr(v), nx, ny, nz, float(alpha), int(iters), _ptr(w))
+    return (v, w.reshape(3, -1)) if return_dual else v
 
 
 def nmse(x, ref) -> float:

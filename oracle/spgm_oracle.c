@@ -18,6 +18,8 @@
  *     D_m(s) = 1/2 |y_m - sum_n A_{m,n} s_n|^2                         (Sec. III, Eq. 4)
  *   - PGM iteration s <- prox_{alpha R}(s - eta grad D(s)), alpha = lambda eta   (Sec. IV, Eq. 5)
  *   - SPGM gradient = gradient of (1/B) sum_{m<B} D_{b_m}(s)          (Sec. IV-A, Eq. 6)
+ *   - other regularisers in place of l1 (extension noted in Sec. III): elastic net and total
+ *     variation of the magnitudes, with their readings in the section that defines them
  *
  * Readings where the paper is silent (each one is listed in the design notes):
  *   - row index m = (i_f * T + i_t) * R + i_r  (frequency-major, then Tx, then Rx);
@@ -233,4 +235,140 @@ void ora_step(const ora_geometry *g, const int32_t *rows, int32_t B, const doubl
 void ora_solve(const ora_geometry *g, const int32_t *rows, int32_t K, int32_t B, const double *y,
                double *s, double eta, double alpha) {
     for (int32_t k = 0; k < K; ++k) ora_step(g, rows + (int64_t)k * B, B, y, s, eta, alpha);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Other regularisers (the paper notes the method extends to other regularisation functionals,
+ * Sec. III); the prox replaces the complex soft threshold in the iteration of Eq. 5.
+ * Readings (no formula in the paper; listed in the design notes):
+ *   - elastic net R(s) = sum_n |s_n| + (mu/2) sum_n |s_n|^2, whose prox is the soft threshold
+ *     followed by the scaling 1/(1 + a mu);
+ *   - total variation of the magnitudes, R(s) = TV(|s|) with the isotropic 3-D TV
+ *     TV(u) = sum_n || (D u)_n ||_2, (D u)_{n,d} = u_{n+e_d} - u_n inside the grid and 0 on the
+ *     upper face of axis d; the prox keeps the phase and replaces the magnitude by the
+ *     non-negative solution of  min_u 1/2 ||u - |v| ||^2 + a TV(u),  computed with the fast
+ *     gradient projection on the dual (Beck & Teboulle 2009) for a given number of iterations:
+ *         u = P+(b - a D^T w),  w <- P_ball(r + D u / (12 a)),  r <- w + ((t_k - 1)/t_{k+1})(w - w_prev),
+ *     t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, t_1 = 1, step 1/(12 a) from ||D||^2 <= 12 in 3-D.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Forward-difference gradient: w[d*N + n] = u[n + e_d] - u[n] inside, 0 on the upper face. */
+void ora_grad3(int32_t nx, int32_t ny, int32_t nz, const double *u, double *w) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int32_t iz = 0; iz < nz; ++iz)
+        for (int32_t iy = 0; iy < ny; ++iy)
+            for (int32_t ix = 0; ix < nx; ++ix) {
+                const int64_t n = ((int64_t)iz * ny + iy) * nx + ix;
+                w[0 * N + n] = ix + 1 < nx ? u[n + 1] - u[n] : 0.0;
+                w[1 * N + n] = iy + 1 < ny ? u[n + nx] - u[n] : 0.0;
+                w[2 * N + n] = iz + 1 < nz ? u[n + (int64_t)nx * ny] - u[n] : 0.0;
+            }
+}
+
+/* Adjoint of ora_grad3: out[n] = sum_d (w_d[n - e_d] if n - e_d is inside) - (w_d[n] if n + e_d is inside). */
+void ora_grad3_adjoint(int32_t nx, int32_t ny, int32_t nz, const double *w, double *out) {
+    const int64_t N = (int64_t)nx * ny * nz, sy = nx, sz = (int64_t)nx * ny;
+    for (int32_t iz = 0; iz < nz; ++iz)
+        for (int32_t iy = 0; iy < ny; ++iy)
+            for (int32_t ix = 0; ix < nx; ++ix) {
+                const int64_t n = ((int64_t)iz * ny + iy) * nx + ix;
+                double acc = 0.0;
+                if (ix > 0) acc += w[0 * N + n - 1];
+                if (ix + 1 < nx) acc -= w[0 * N + n];
+                if (iy > 0) acc += w[1 * N + n - sy];
+                if (iy + 1 < ny) acc -= w[1 * N + n];
+                if (iz > 0) acc += w[2 * N + n - sz];
+                if (iz + 1 < nz) acc -= w[2 * N + n];
+                out[n] = acc;
+            }
+}
+
+/* Elastic-net prox in place: v <- S_a(v) / (1 + a mu). */
+void ora_prox_elastic(double *v, int64_t N, double a, double mu) {
+    ora_prox_l1(v, N, a);
+    const double scale = 1.0 / (1.0 + a * mu);
+    for (int64_t n = 0; n < 2 * N; ++n) v[n] *= scale;
+}
+
+/* Magnitude-TV prox in place on complex v (grid nx x ny x nz), `iters` dual iterations.
+ * w_out (3N doubles, may be NULL) receives the final dual field w, from which the returned
+ * magnitude is u = max(0, |v| - a D^T w). */
+void ora_prox_tv_magnitude(double *v, int32_t nx, int32_t ny, int32_t nz, double a, int32_t iters,
+                           double *w_out) {
+    const int64_t N = (int64_t)nx * ny * nz;
+    double *b = (double *)malloc(sizeof(double) * N);
+    double *u = (double *)malloc(sizeof(double) * N);
+    double *t = (double *)malloc(sizeof(double) * N);
+    double *w = (double *)calloc(3 * (size_t)N, sizeof(double));
+    double *w_prev = (double *)calloc(3 * (size_t)N, sizeof(double));
+    double *r = (double *)calloc(3 * (size_t)N, sizeof(double));
+    double *g = (double *)malloc(sizeof(double) * 3 * N);
+    for (int64_t n = 0; n < N; ++n) b[n] = hypot(v[2 * n], v[2 * n + 1]);
+    if (a > 0.0) {
+        double tk = 1.0;
+        for (int32_t k = 0; k < iters; ++k) {
+            /* primal point of the extrapolated dual, projected on u >= 0 */
+            ora_grad3_adjoint(nx, ny, nz, r, t);
+            for (int64_t n = 0; n < N; ++n) u[n] = fmax(0.0, b[n] - a * t[n]);
+            /* dual ascent step and projection of every voxel's 3-vector on the unit ball */
+            ora_grad3(nx, ny, nz, u, g);
+            memcpy(w_prev, w, sizeof(double) * 3 * N);
+            for (int64_t n = 0; n < N; ++n) {
+                double p0 = r[n] + g[n] / (12.0 * a);
+                double p1 = r[N + n] + g[N + n] / (12.0 * a);
+                double p2 = r[2 * N + n] + g[2 * N + n] / (12.0 * a);
+                const double norm = sqrt(p0 * p0 + p1 * p1 + p2 * p2);
+                if (norm > 1.0) {
+                    p0 /= norm;
+                    p1 /= norm;
+                    p2 /= norm;
+                }
+                w[n] = p0;
+                w[N + n] = p1;
+                w[2 * N + n] = p2;
+            }
+            /* momentum */
+            const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
+            const double beta = (tk - 1.0) / tn;
+            for (int64_t i = 0; i < 3 * N; ++i) r[i] = w[i] + beta * (w[i] - w_prev[i]);
+            tk = tn;
+        }
+        ora_grad3_adjoint(nx, ny, nz, w, t);
+        for (int64_t n = 0; n < N; ++n) u[n] = fmax(0.0, b[n] - a * t[n]);
+    } else {
+        memcpy(u, b, sizeof(double) * N);
+    }
+    if (w_out) memcpy(w_out, w, sizeof(double) * 3 * N);
+    /* keep the phase: v <- u v/|v| (0 where v = 0) */
+    for (int64_t n = 0; n < N; ++n) {
+        if (b[n] > 0.0) {
+            const double scale = u[n] / b[n];
+            v[2 * n] *= scale;
+            v[2 * n + 1] *= scale;
+        } else {
+            v[2 * n] = 0.0;
+            v[2 * n + 1] = 0.0;
+        }
+    }
+    free(b);
+    free(u);
+    free(t);
+    free(w);
+    free(w_prev);
+    free(r);
+    free(g);
+}
+
+/* One iteration of Eq. 5 with the minibatch gradient of Eq. 6 and the prox of the chosen
+ * regulariser: kind 0 = l1, 1 = elastic net (mu), 2 = magnitude TV (tv_iters). */
+void ora_step_reg(const ora_geometry *g, const int32_t *rows, int32_t B, const double *y, double *s, double eta,
+                  double alpha, int32_t kind, double mu, int32_t tv_iters) {
+    const int64_t N = ora_num_voxels(g);
+    double *grad = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    ora_stochastic_gradient(g, rows, B, y, s, grad);
+    for (int64_t n = 0; n < 2 * N; ++n) s[n] -= eta * grad[n];
+    if (kind == 1) ora_prox_elastic(s, N, alpha, mu);
+    else if (kind == 2) ora_prox_tv_magnitude(s, g->nx, g->ny, g->nz, alpha, tv_iters, NULL);
+    else ora_prox_l1(s, N, alpha);
+    free(grad);
 }
