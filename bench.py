@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--workload c1]
        --workload c3     ragged batch of 96 scenes
        --workload c1k32  32 scenes of the c1 geometry through the shared-geometry batched path
        --workload c1s    c1 geometry with structured (16 f x 16 Tx x 16 Rx) minibatches
+       --workload c1tv   c1 with the magnitude-TV prox (10 dual iterations per step) on a blocky scene
 """
 import argparse
 import hashlib
@@ -38,9 +39,13 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 SLOTS_PER_ENTRY = 9
 STEP_SIZES = os.path.join(ROOT, "tests", "golden", "step_sizes.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
-SOURCES = [os.path.join(ROOT, "paper_2509_00774_amd", "csrc", "spgm.hip"),
-           os.path.join(ROOT, "paper_2509_00774_amd", "csrc", "spgm_mm.inc"),
-           os.path.join(ROOT, "include", "spgm.h")]
+SOURCES = [os.path.join(ROOT, "paper_2509_00774_amd", "csrc", name)
+           for name in ("spgm.hip", "spgm_mm.inc", "spgm_sf.inc", "spgm_reg.inc")] + [
+    os.path.join(ROOT, "include", "spgm.h")]
+# Total-variation prox: algorithmic bytes per voxel and dual iteration (read b, r, w; write w, r
+# as three float32 components each).
+TV_BYTES_PER_VOXEL = 4 + 4 * 12
+HBM_PEAK = 8.0e12
 
 
 def log(*a):
@@ -71,7 +76,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4", "c3", "c1k32", "c1s"],
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4", "c3", "c1k32", "c1s", "c1tv"],
                     help="c3 is the ragged batch of 96 scenes advanced together")
     ap.add_argument("--cpu-iters", type=int, default=5, help="iterations of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -111,6 +116,8 @@ def main():
         return bench_batched(args, torch, binding, dev)
     if wl == "c1s":
         return bench_structured(args, torch, binding, dev)
+    if wl == "c1tv":
+        return bench_tv(args, torch, binding, dev)
     cfg = W.CONFIGS[wl]
     geom = W.config_geometry(wl)
     M, N = W.dims(geom)
@@ -545,6 +552,117 @@ def bench_structured(args, torch, binding, dev):
                      "traffic": None, "flops_per_launch": flops, "avg_launch_ms": round(kavg * 1e3, 5),
                      "sf_fwd_ms": round(fwd_avg * 1e3, 5), "sf_adj_ms": round(adj_avg * 1e3, 5),
                      "factors_per_launch": nf * (nt + nr) * N},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def bench_tv(args, torch, binding, dev):
+    """c1 geometry and minibatches with the magnitude-TV prox in place of the soft threshold
+    (10 dual iterations per step) on a blocky random-phase scene.  The step is the same
+    gradient evaluation followed by the TV prox; the TV dual iteration is timed on its own."""
+    cfg = W.CONFIGS["c1"]
+    geom = W.config_geometry("c1")
+    M, N = W.dims(geom)
+    B = cfg["B"]
+    K, Wm = args.steps, args.warmup
+    tv_iters = 10
+    sj = json.load(open(STEP_SIZES))["c1"]
+    eta = float(np.float32(sj["eta"]))
+    rows = W.config_rows("c1", K=max(Wm + K, args.cpu_iters))
+    s_true = W.blocky_field(cfg["grid"], n_boxes=6, noise=0.0, seed=cfg["seed"] + 11)
+    plan = binding.Plan(geom)
+    splits = None if args.no_tune else plan.spgm_plan_autotune(B)
+    all_rows = torch.arange(M, dtype=torch.int32, device=dev)
+    y0 = plan.spgm_forward(all_rows, torch.from_numpy(s_true.astype(np.complex64)).to(dev))
+    y_host = W.add_noise(y0.cpu().numpy().astype(np.complex128), cfg["snr_db"], seed=cfg["seed"] + 12)
+    y = torch.from_numpy(y_host.astype(np.complex64)).to(dev)
+    # TV weight: the stored l1 weight of the c1 workload (from the oracle), times the step size
+    alpha = float(np.float32(sj["lambda"] * eta))
+    rows_d = torch.from_numpy(rows).to(dev)
+    n_par = args.cpu_iters
+    s_par = torch.zeros(N, dtype=torch.complex64, device=dev)
+    plan.spgm_solve_reg(rows_d[:n_par].contiguous(), y, s_par, eta, alpha, binding.REG_TV_MAGNITUDE,
+                        tv_iters=tv_iters)
+    s_par_host = s_par.cpu().numpy()
+    s = torch.zeros(N, dtype=torch.complex64, device=dev)
+    if Wm:
+        plan.spgm_solve_reg(rows_d[:Wm].contiguous(), y, s, eta, alpha, binding.REG_TV_MAGNITUDE, tv_iters=tv_iters)
+    s.zero_()
+    timed = rows_d[Wm:Wm + K].contiguous()
+    plan.spgm_plan_timing(True)
+    plan.spgm_plan_timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.spgm_solve_reg(timed, y, s, eta, alpha, binding.REG_TV_MAGNITUDE, tv_iters=tv_iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwd_ms, fwd_n, adj_ms, adj_n = plan.spgm_plan_timing_read()
+    plan.spgm_plan_timing(False)
+    assert plan.spgm_plan_status() == 0
+    dt = t1 - t0
+    # TV dual iteration: slope of the prox time between 8 and 208 dual iterations, HIP events on
+    # the stream the prox is launched on (includes the gaps between back-to-back launches).
+    v = s.clone()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    stream = torch.cuda.current_stream()
+    plan.spgm_prox(v, alpha, binding.REG_TV_MAGNITUDE, tv_iters=208)
+    ev[0].record(stream)
+    plan.spgm_prox(v, alpha, binding.REG_TV_MAGNITUDE, tv_iters=8)
+    ev[1].record(stream)
+    ev[2].record(stream)
+    plan.spgm_prox(v, alpha, binding.REG_TV_MAGNITUDE, tv_iters=208)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    tv_iter_s = (ev[2].elapsed_time(ev[3]) - ev[0].elapsed_time(ev[1])) * 1e-3 / 200.0
+    tv_bytes = float(TV_BYTES_PER_VOXEL) * N
+    fwd_avg, adj_avg = fwd_ms / max(fwd_n, 1) * 1e-3, adj_ms / max(adj_n, 1) * 1e-3
+    entries = float(B) * N
+    kname, kavg = ("k_fwd_tile", fwd_avg) if fwd_avg >= adj_avg else ("k_adj_tile", adj_avg)
+    achieved = entries * SLOTS_PER_ENTRY / kavg / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
+    log("timed %d TV-regularised iterations in %.4f s (%.4f ms each); forward %.4f ms, adjoint %.4f ms, "
+        "TV dual iteration %.2f us" % (K, dt, 1e3 * dt / K, 1e3 * fwd_avg, 1e3 * adj_avg, 1e6 * tv_iter_s))
+    cpu = None
+    rel = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.Oracle(geom)
+        y_orc = W.add_noise(orc.forward(np.arange(M), s_true), cfg["snr_db"], seed=cfg["seed"] + 12)
+        log("oracle: %d TV-regularised SPGM iterations, %d threads" % (n_par, oracle.num_threads()))
+        c0 = time.perf_counter()
+        ref = np.zeros(N, dtype=np.complex128)
+        for k in range(n_par):
+            ref = orc.step_reg(rows[k], y_orc, ref, eta, alpha, 2, tv_iters=tv_iters)
+        c1 = time.perf_counter()
+        rel = oracle.rel_l2(s_par_host, ref)
+        cpu = {"value": round(entries * n_par / (c1 - c0) / 1e9, 4), "unit": "Gentries/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d TV-regularised SPGM iterations of the same workload (B=%d rows x N=%d voxels, "
+                         "%d dual iterations per prox), FP64, %.1f s" % (n_par, B, N, tv_iters, c1 - c0)}
+        log("oracle: %.1f s, GPU iterate %d rel_l2 vs oracle %.3e" % (c1 - c0, n_par, rel))
+    out = {
+        "metric": "projector Gentries/s (A_B s + A_B^H r) and SPGM iters/s at fixed NMSE vs oracle",
+        "value": round(entries * K / dt / 1e9, 2), "unit": "Gentries/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": round(1e3 * dt / K, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c1 (32 Tx + 32 Rx, 64 frequencies, 64x64x32 voxels, B=4096) with the magnitude-TV "
+                               "prox, %d dual iterations per step, blocky random-phase scene" % tv_iters,
+                   "M": M, "N": N, "B": B, "tv_iters": tv_iters, "hip_graph": False,
+                   "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]}},
+        "spgm_iters_per_s": round(K / dt, 2),
+        "rel_l2_vs_oracle": None if rel is None else float("%.3e" % rel),
+        "rel_l2_vs_oracle_after_iters": n_par,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
+                     "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
+                     "avg_launch_ms": round(kavg * 1e3, 5), "fwd_tile_ms": round(fwd_avg * 1e3, 5),
+                     "adj_tile_ms": round(adj_avg * 1e3, 5)},
+        "tv_dual_iteration": {"bound": "hbm", "kernel": "k_tv_iter<false>", "us": round(tv_iter_s * 1e6, 3),
+                              "bytes": tv_bytes, "achieved": round(tv_bytes / tv_iter_s / 1e9, 1),
+                              "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(tv_bytes / tv_iter_s / HBM_PEAK, 4),
+                              "share_of_step": round(tv_iters * tv_iter_s / (dt / K), 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

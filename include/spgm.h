@@ -225,6 +225,42 @@ int spgm_solve_structured(spgm_plan *plan, const int32_t *f_idx_d, int32_t nf, c
                           int32_t nt, const int32_t *r_idx_d, int32_t nr, int32_t iters, const void *y_d,
                           void *s_d, float eta, float alpha, void *stream);
 
+/* Other regularisers in place of the l1 norm of Eq. 3 (the extension noted in Sec. III); the
+ * prox of Eq. 5 changes, the data-fidelity gradient does not.
+ *   SPGM_REG_L1:           R(s) = sum_n |s_n|; prox S_alpha (as spgm_step).
+ *   SPGM_REG_ELASTIC_NET:  R(s) = sum_n |s_n| + (mu/2) sum_n |s_n|^2; prox S_alpha(v) / (1 + alpha mu).
+ *   SPGM_REG_TV_MAGNITUDE: R(s) = TV(|s|), the isotropic 3-D total variation of the magnitudes with
+ *       forward differences on the voxel grid (zero on the upper face of each axis).  The prox keeps
+ *       the phase of v and replaces |v| by the minimiser of 1/2 ||u - |v| ||^2 + alpha TV(u) over
+ *       u >= 0, approximated by `tv_iters` iterations of fast gradient projection on the dual
+ *       (Beck and Teboulle), started from a zero dual at every call (one launch per iteration).
+ * mu: finite, >= 0 (elastic net only).  tv_iters: 0 .. 100000 (TV only; 0 or alpha = 0 leave v
+ * unchanged).  The TV prox allocates 68 bytes per voxel of plan workspace on first use
+ * (hipMalloc, synchronous). */
+typedef enum spgm_reg_kind {
+    SPGM_REG_L1 = 0,
+    SPGM_REG_ELASTIC_NET = 1,
+    SPGM_REG_TV_MAGNITUDE = 2
+} spgm_reg_kind;
+
+typedef struct spgm_regularizer {
+    int32_t kind;      /* spgm_reg_kind */
+    float mu;          /* elastic-net weight of the squared norm */
+    int32_t tv_iters;  /* dual iterations of the TV prox */
+} spgm_regularizer;
+
+/* v_d <- prox_{alpha R}(v_d) in place; v_d: complex64[N]; alpha finite, >= 0. */
+int spgm_prox(spgm_plan *plan, const spgm_regularizer *reg, void *v_d, float alpha, void *stream);
+
+/* One SPGM iteration (as spgm_step) with the prox of `reg`:
+ *     s <- prox_{alpha R}( s - (eta/B) A_B^H (A_B s - y_B) ). */
+int spgm_step_reg(spgm_plan *plan, const spgm_regularizer *reg, const int32_t *rows_d, int32_t B,
+                  const void *y_d, void *s_d, float eta, float alpha, void *stream);
+
+/* `iters` calls of spgm_step_reg; iteration k uses rows_d[k*B .. k*B + B - 1]. */
+int spgm_solve_reg(spgm_plan *plan, const spgm_regularizer *reg, const int32_t *rows_d, int32_t iters,
+                   int32_t B, const void *y_d, void *s_d, float eta, float alpha, void *stream);
+
 /* Ragged batches of independent scenes (each with its own array, band and grid) advanced
  * together: every SPGM iteration of every scene is one launch per phase (sort, forward tile,
  * row reduction, adjoint tile, column reduction with the prox step).  The tile phases walk a

@@ -30,12 +30,17 @@ PHASE_NAIVE32 = 2
 MM_BF16 = 0
 MM_FP16 = 1
 
+REG_L1 = 0
+REG_ELASTIC_NET = 1
+REG_TV_MAGNITUDE = 2
+
 EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_forward", "spgm_adjoint",
             "spgm_step", "spgm_solve", "spgm_plan_status", "spgm_last_error", "spgm_plan_timing",
             "spgm_plan_timing_read", "spgm_unrolled_vjp_step", "spgm_solve_graph", "spgm_plan_autotune",
             "spgm_batch_create", "spgm_batch_destroy", "spgm_batch_plan", "spgm_batch_solve", "spgm_batch_status",
             "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched",
-            "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured")
+            "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured",
+            "spgm_prox", "spgm_step_reg", "spgm_solve_reg")
 
 _dp = C.POINTER(C.c_double)
 
@@ -48,6 +53,11 @@ class SpgmGeometry(C.Structure):
         ("tx_xyz", _dp), ("rx_xyz", _dp), ("freq_hz", _dp), ("pulse", _dp),
         ("centre", C.c_double * 3), ("pitch", C.c_double * 3), ("c", C.c_double),
     ]
+
+
+class SpgmRegularizer(C.Structure):
+    """Mirror of ``spgm_regularizer``."""
+    _fields_ = [("kind", C.c_int32), ("mu", C.c_float), ("tv_iters", C.c_int32)]
 
 
 class SpgmError(RuntimeError):
@@ -97,6 +107,9 @@ def load_library(path: str = LIB_PATH):
         "spgm_adjoint_structured": [vp, vp, i32, vp, i32, vp, i32, vp, vp, vp],
         "spgm_step_structured": [vp, vp, i32, vp, i32, vp, i32, vp, vp, f32, f32, vp],
         "spgm_solve_structured": [vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, f32, f32, vp],
+        "spgm_prox": [vp, C.POINTER(SpgmRegularizer), vp, f32, vp],
+        "spgm_step_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, vp, vp, f32, f32, vp],
+        "spgm_solve_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, i32, vp, vp, f32, f32, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -233,6 +246,36 @@ class Plan:
         _check(self._lib.spgm_solve(self._h, _dev(rows_table, torch.int32, "rows_table"), int(K), int(B),
                                     _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
                                     float(eta), float(alpha), _stream_ptr(stream)))
+        return s
+
+    # --- other regularisers: kind REG_L1, REG_ELASTIC_NET (mu) or REG_TV_MAGNITUDE (tv_iters) ---
+    def spgm_prox(self, v, alpha, kind, mu=0.0, tv_iters=0, stream=None):
+        import torch
+        reg = SpgmRegularizer(int(kind), float(mu), int(tv_iters))
+        _check(self._lib.spgm_prox(self._h, C.byref(reg), _dev(v, torch.complex64, "v", self.N), float(alpha),
+                                   _stream_ptr(stream)))
+        return v
+
+    def spgm_step_reg(self, rows, y, s, eta, alpha, kind, mu=0.0, tv_iters=0, stream=None):
+        import torch
+        reg = SpgmRegularizer(int(kind), float(mu), int(tv_iters))
+        B = rows.numel()
+        _check(self._lib.spgm_step_reg(self._h, C.byref(reg), _dev(rows, torch.int32, "rows"), B,
+                                       _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
+                                       float(eta), float(alpha), _stream_ptr(stream)))
+        return s
+
+    def spgm_solve_reg(self, rows_table, y, s, eta, alpha, kind, mu=0.0, tv_iters=0, stream=None):
+        """``rows_table``: int32 tensor of shape (iters, B)."""
+        import torch
+        if rows_table.dim() != 2:
+            raise ValueError("rows_table must be 2-D (iters, B)")
+        K, B = rows_table.shape
+        reg = SpgmRegularizer(int(kind), float(mu), int(tv_iters))
+        _check(self._lib.spgm_solve_reg(self._h, C.byref(reg), _dev(rows_table, torch.int32, "rows_table"), int(K),
+                                        int(B), _dev(y, torch.complex64, "y", self.M),
+                                        _dev(s, torch.complex64, "s", self.N), float(eta), float(alpha),
+                                        _stream_ptr(stream)))
         return s
 
     def spgm_unrolled_vjp_step(self, rows, y, s, eta, tau, sbar_next, sbar, eta_bar, tau_bar, stream=None):

@@ -961,6 +961,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 
 #include "spgm_mm.inc"
 #include "spgm_sf.inc"
+#include "spgm_reg.inc"
 
 // ------------------------------------------------------------------------------------------
 // Host side
@@ -1048,6 +1049,9 @@ struct spgm_plan {
     // structured minibatches: measurement index of every row of the current minibatch
     int32_t *d_sf_rows = nullptr;
     size_t sf_rows_cap = 0;
+    // TV prox: magnitudes b [voxel] and the dual state w[2], r[2] [voxel] (ping-pong)
+    float *d_tv_b = nullptr;
+    float4 *d_tv_state = nullptr;
 };
 
 // A batch of independent scenes (one plan each) advanced together.
@@ -1238,6 +1242,84 @@ int step_sorted(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const
     k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, nullptr, s,
                                                              eta / (float)B, alpha);
     return launch_check("column reduce");
+}
+
+// ---------------------------------------------------------------- other regularisers
+constexpr int kMaxTVIters = 100000;
+
+int check_reg(const spgm_regularizer *reg) {
+    if (!reg) return fail(SPGM_E_INVALID, "spgm: regularizer is NULL");
+    if (reg->kind < SPGM_REG_L1 || reg->kind > SPGM_REG_TV_MAGNITUDE)
+        return fail(SPGM_E_INVALID, "spgm: unknown regularizer kind %d", (int)reg->kind);
+    if (reg->kind == SPGM_REG_ELASTIC_NET && !(std::isfinite(reg->mu) && reg->mu >= 0))
+        return fail(SPGM_E_INVALID, "spgm: elastic-net mu must be finite and >= 0");
+    if (reg->kind == SPGM_REG_TV_MAGNITUDE && (reg->tv_iters < 0 || reg->tv_iters > kMaxTVIters))
+        return fail(SPGM_E_INVALID, "spgm: tv_iters must be in [0, %d]", kMaxTVIters);
+    return SPGM_OK;
+}
+
+int ensure_tv(spgm_plan *p) {
+    if (p->d_tv_b) return SPGM_OK;
+    if (hipMalloc(&p->d_tv_b, sizeof(float) * (size_t)p->N) != hipSuccess) {
+        p->d_tv_b = nullptr;
+        return fail(SPGM_E_NOMEM, "spgm: TV workspace allocation failed");
+    }
+    if (hipMalloc(&p->d_tv_state, sizeof(float4) * 4 * (size_t)p->N) != hipSuccess) {
+        hipFree(p->d_tv_b);
+        p->d_tv_b = nullptr;
+        p->d_tv_state = nullptr;
+        return fail(SPGM_E_NOMEM, "spgm: TV workspace allocation failed");
+    }
+    return SPGM_OK;
+}
+
+float elastic_scale(float alpha, float mu) { return (float)(1.0 / (1.0 + (double)alpha * (double)mu)); }
+
+// TV prox of v in place (workspace allocated): `iters` dual iterations and the final primal point.
+int run_tv_prox(spgm_plan *p, float2 *v, float alpha, int iters, hipStream_t st) {
+    if (alpha == 0.f || iters == 0) return SPGM_OK;
+    const TVGrid g{p->geo.nx, p->geo.ny, p->geo.nz, (int)p->N, p->geo.nx * p->geo.ny};
+    const int nb = (g.N + kRegThreads - 1) / kRegThreads;
+    float4 *w[2] = {p->d_tv_state, p->d_tv_state + p->N};
+    float4 *r[2] = {p->d_tv_state + 2 * p->N, p->d_tv_state + 3 * p->N};
+    const float inv12a = (float)(1.0 / (12.0 * (double)alpha));
+    double t = 1.0;
+    int rc;
+    for (int k = 1; k <= iters; ++k) {
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        const float beta = (float)((t - 1.0) / tn);
+        t = tn;
+        if (k == 1)
+            k_tv_iter<true><<<nb, kRegThreads, 0, st>>>(g, v, p->d_tv_b, nullptr, nullptr, w[1], r[1], alpha, inv12a,
+                                                        0.f);
+        else
+            k_tv_iter<false><<<nb, kRegThreads, 0, st>>>(g, v, p->d_tv_b, r[(k - 1) & 1], w[(k - 1) & 1], w[k & 1],
+                                                         r[k & 1], alpha, inv12a, beta);
+        if ((rc = launch_check("tv dual iteration"))) return rc;
+    }
+    k_tv_finish<<<nb, kRegThreads, 0, st>>>(g, v, p->d_tv_b, w[iters & 1], alpha);
+    return launch_check("tv finish");
+}
+
+// One iteration on already sorted rows with the prox of `reg` (validated, workspace allocated).
+int step_sorted_reg(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const float2 *y, float2 *s, float eta,
+                    float alpha, const spgm_regularizer &reg, hipStream_t st) {
+    if (reg.kind == SPGM_REG_L1) return step_sorted(p, srt, rows, B, y, s, eta, alpha, st);
+    int rc;
+    if ((rc = run_forward_partials(p, srt, s, B, st))) return rc;
+    if ((rc = run_row_reduce(p, srt, rows, B, y, nullptr, p->d_rs, st))) return rc;
+    if ((rc = run_adjoint_partials(p, srt, B, st))) return rc;
+    const int nb = (int)((p->N + kRegThreads - 1) / kRegThreads);
+    if (reg.kind == SPGM_REG_ELASTIC_NET) {
+        k_col_reduce_elastic<<<nb, kRegThreads, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, s, eta / (float)B,
+                                                         alpha, elastic_scale(alpha, reg.mu));
+        return launch_check("column reduce (elastic net)");
+    }
+    // gradient step only (a zero threshold leaves every value unchanged), then the TV prox
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, nullptr, s,
+                                                             eta / (float)B, 0.f);
+    if ((rc = launch_check("column reduce"))) return rc;
+    return run_tv_prox(p, s, alpha, reg.tv_iters, st);
 }
 
 int ensure_vjp(spgm_plan *p) {
@@ -1654,6 +1736,8 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_gpart);
     hipFree(p->d_srt_all);
     hipFree(p->d_vjp);
+    hipFree(p->d_tv_b);
+    hipFree(p->d_tv_state);
     hipFree(p->d_vjp_part);
     hipFree(p->d_mm_s);
     hipFree(p->d_mm_part);
@@ -1765,6 +1849,66 @@ int spgm_solve(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, cons
     if (iters == 0) return ok();
     if ((rc = solve_launches(p, rows, iters, B, (const float2 *)y, (float2 *)s, eta, alpha, (hipStream_t)stream)))
         return rc;
+    return ok();
+}
+
+int spgm_prox(spgm_plan *p, const spgm_regularizer *reg, void *v, float alpha, void *stream) {
+    int rc;
+    if (!p) return fail(SPGM_E_INVALID, "spgm: plan is NULL");
+    if ((rc = check_reg(reg))) return rc;
+    if (!v) return fail(SPGM_E_INVALID, "spgm_prox: v must be non-NULL");
+    if (!(std::isfinite(alpha) && alpha >= 0)) return fail(SPGM_E_INVALID, "spgm: alpha must be finite and >= 0");
+    DeviceGuard guard(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    if (reg->kind == SPGM_REG_TV_MAGNITUDE) {
+        if ((rc = ensure_tv(p))) return rc;
+        if ((rc = run_tv_prox(p, (float2 *)v, alpha, reg->tv_iters, st))) return rc;
+        return ok();
+    }
+    const float scale = reg->kind == SPGM_REG_ELASTIC_NET ? elastic_scale(alpha, reg->mu) : 1.f;
+    k_prox_elastic<<<(int)((p->N + kRegThreads - 1) / kRegThreads), kRegThreads, 0, st>>>((float2 *)v, (int)p->N,
+                                                                                        alpha, scale);
+    if ((rc = launch_check("prox"))) return rc;
+    return ok();
+}
+
+int spgm_step_reg(spgm_plan *p, const spgm_regularizer *reg, const int32_t *rows, int32_t B, const void *y, void *s,
+                  float eta, float alpha, void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    if ((rc = check_reg(reg))) return rc;
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B))) return rc;
+    if (reg->kind == SPGM_REG_TV_MAGNITUDE && (rc = ensure_tv(p))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    if ((rc = step_sorted_reg(p, p->d_srt, rows, B, (const float2 *)y, (float2 *)s, eta, alpha, *reg, st)))
+        return rc;
+    return ok();
+}
+
+int spgm_solve_reg(spgm_plan *p, const spgm_regularizer *reg, const int32_t *rows, int32_t iters, int32_t B,
+                   const void *y, void *s, float eta, float alpha, void *stream) {
+    int rc;
+    if (!p) return fail(SPGM_E_INVALID, "spgm: plan is NULL");
+    if ((rc = check_reg(reg))) return rc;
+    DeviceGuard guard(p->device);
+    if ((rc = solve_prepare(p, rows, iters, B, y, s, eta, alpha))) return rc;
+    if (iters == 0) return ok();
+    if (reg->kind == SPGM_REG_TV_MAGNITUDE && (rc = ensure_tv(p))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int per = (int)std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
+    for (int k0 = 0; k0 < iters; k0 += per) {
+        const int cnt = std::min(per, iters - k0);
+        const int32_t *rk = rows + (size_t)k0 * B;
+        if ((rc = run_sort(p, rk, B, cnt, p->d_srt_all, st))) return rc;
+        for (int k = 0; k < cnt; ++k) {
+            if ((rc = step_sorted_reg(p, p->d_srt_all + (size_t)k * B, rk + (size_t)k * B, B, (const float2 *)y,
+                                      (float2 *)s, eta, alpha, *reg, st)))
+                return rc;
+        }
+    }
     return ok();
 }
 

@@ -119,6 +119,21 @@ def patch_scene(grid, density, seed=0, patch=32, depths=(16, 32, 48)):
     return s, np.flatnonzero(s)
 
 
+def blocky_field(grid, n_boxes=6, noise=0.05, seed=0):
+    """Complex volume whose magnitude is a sum of constant boxes plus |Gaussian| noise and whose
+    phase is uniform: the piecewise-constant images total-variation priors are meant for."""
+    nx, ny, nz = (int(v) for v in grid)
+    rng = np.random.default_rng(seed)
+    mag = np.zeros((nz, ny, nx))
+    for _ in range(n_boxes):
+        lo = [int(rng.integers(0, n)) for n in (nz, ny, nx)]
+        hi = [int(rng.integers(l + 1, n + 1)) for l, n in zip(lo, (nz, ny, nx))]
+        mag[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] += rng.uniform(0.3, 1.0)
+    mag = mag + noise * np.abs(rng.standard_normal(mag.shape))
+    ph = rng.uniform(0.0, 2 * np.pi, size=mag.shape)
+    return (mag * np.exp(1j * ph)).reshape(-1)
+
+
 def add_noise(y0, snr_db, seed=0):
     """y0 + w, w circular complex Gaussian with variance mean|y0|^2 * 10^(-snr/10)."""
     rng = np.random.default_rng(seed)

@@ -48,6 +48,12 @@ def test_null_and_range_errors(lib):
     assert lib.spgm_adjoint(None, C.c_void_p(8), 4, C.c_void_p(8), C.c_void_p(8), None) == bd.SPGM_E_INVALID
     assert lib.spgm_step(None, C.c_void_p(8), 4, C.c_void_p(8), C.c_void_p(8), 1.0, 0.0, None) == bd.SPGM_E_INVALID
     assert lib.spgm_solve(None, C.c_void_p(8), 1, 4, C.c_void_p(8), C.c_void_p(8), 1.0, 0.0, None) == bd.SPGM_E_INVALID
+    reg = bd.SpgmRegularizer(bd.REG_TV_MAGNITUDE, 0.0, 4)
+    assert lib.spgm_prox(None, C.byref(reg), C.c_void_p(8), 0.1, None) == bd.SPGM_E_INVALID
+    assert lib.spgm_step_reg(None, C.byref(reg), C.c_void_p(8), 4, C.c_void_p(8), C.c_void_p(8), 1.0, 0.0,
+                             None) == bd.SPGM_E_INVALID
+    assert lib.spgm_solve_reg(None, C.byref(reg), C.c_void_p(8), 1, 4, C.c_void_p(8), C.c_void_p(8), 1.0, 0.0,
+                              None) == bd.SPGM_E_INVALID
     assert lib.spgm_plan_dims(None, None, None) == bd.SPGM_E_INVALID
     st = C.c_int32()
     assert lib.spgm_plan_status(None, C.byref(st)) == bd.SPGM_E_INVALID
