@@ -515,15 +515,18 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
             // block length: rows i0 .. i0+len-1 all use the same G antenna
             const int q = lane & 15;
             const int iq = i0 + q;
-            const bool stop = iq >= cnt || (q > 0 && (__float_as_int(rinfo[min(iq, cnt - 1)].z) & kNewG));
+            const int wq = __float_as_int(rinfo[min(iq, cnt - 1)].z);  // lane q: word of row i0 + q
+            const bool stop = iq >= cnt || (q > 0 && (wq & kNewG));
             const unsigned long long stops = __ballot(stop) & 0xffffull;
             const int len = stops ? __ffsll((long long)stops) - 1 : 16;
+            // pair changes of the block as a scalar bit mask: the per-row branch needs no lane read
+            const unsigned long long pairs = __ballot(wq & kNewPair) & 0xffffull;
 #pragma unroll
             for (int qq = 0; qq < 16; ++qq) {
                 if (qq < len) {
                     const float4 ri = rinfo[i0 + qq];
-                    const int word = uniform(__float_as_int(ri.z));
-                    if (word & kNewPair) {
+                    if ((pairs >> qq) & 1ull) {
+                        const int word = __builtin_amdgcn_readlane(wq, qq);
                         const typename P::LE *lp = lbase + row_l(word) * kBrick;
 #pragma unroll
                         for (int p = 0; p < kP; ++p) {
@@ -553,9 +556,14 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
                     }
                     accr[qq] = ar;
                     acci[qq] = ai;
+                } else {
+                    // defined values for the rows past the block end (their sums are discarded),
+                    // so that no accumulator stays live across the reduction and the lane swaps
+                    // below can work in place
+                    accr[qq] = 0.f;
+                    acci[qq] = 0.f;
                 }
             }
-            // Rows at or beyond len hold stale values; their sums are discarded below.
             const float tr = wave_transpose_sum16(accr, b3, b2);
             const float ti = wave_transpose_sum16(acci, b3, b2);
             const int row = lane >> 2;
@@ -682,19 +690,30 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
     int wb, we, nsub;
     wave_rows(r0, r1, wave, wb, we, nsub);
     const float4 *rinfo = sm.rowinfo + wave * kWave;
-    const float2 *rvals = sm.rowv + wave * kWave;
 
     for (int j = 0; j < nsub; ++j) {
         __syncthreads();
         const int my_row = stage_rows<MODE>(g, sm, srt, r0, r1, j);
-        if (my_row >= 0) sm.rowv[threadIdx.x] = rs[my_row];
+        // Row data for the loop: (policy words, residual) in one LDS entry per row; the row word
+        // stays in this lane's register and the pair changes of the sub-chunk become a scalar bit
+        // mask, so the per-row branch waits for no LDS read.
+        int my_word = 0;
+        if (my_row >= 0) {
+            float4 e = sm.rowinfo[threadIdx.x];
+            my_word = __float_as_int(e.z);
+            const float2 rv = rs[my_row];
+            e.z = rv.x;
+            e.w = rv.y;
+            sm.rowinfo[threadIdx.x] = e;
+        }
+        const unsigned long long pairs = __ballot(my_word & kNewPair);
         __syncthreads();
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         for (int i = 0; i < cnt; ++i) {
             const float4 ri = rinfo[i];
-            const float2 rv = rvals[i];
-            const int word = uniform(__float_as_int(ri.z));
-            if (word & kNewPair) {
+            const float2 rv = make_float2(ri.z, ri.w);
+            if ((pairs >> i) & 1ull) {
+                const int word = __builtin_amdgcn_readlane(my_word, i);
                 // close the previous pair and set up the new one
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
