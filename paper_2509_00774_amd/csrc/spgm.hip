@@ -417,29 +417,48 @@ __device__ __forceinline__ void wave_rows(int r0, int r1, int w, int &wb, int &w
     nsub = per / kWave;  // sub-chunks of 64 rows per wave (same for every wave)
 }
 
-// Stage sub-chunk j: thread t holds row wb(t/64) + 64 j + t%64 of its wave's run.  Returns the
-// sorted row index (or -1).  Row data: the policy's two words (f/c and the per-brick reference
-// phase for COMP32) and the packed row word.
-template <int MODE>
-__device__ __forceinline__ int stage_rows(const Geo &g, const TileSmem &sm, const int4 *__restrict__ srt, int r0,
-                                          int r1, int j) {
+// Global part of staging sub-chunk j: thread t holds row wb(t/64) + 64 j + t%64 of its wave's
+// run; it loads that sorted row and its predecessor's antennas (pg = -1 for the first row of the
+// run, r = -1 past its end).  Issued one sub-chunk ahead, the loads are in flight while the rows
+// of the current sub-chunk are processed.
+struct RowFetch {
+    int r, pg, pl;
+    int4 info;
+};
+
+__device__ __forceinline__ RowFetch fetch_rows(const int4 *__restrict__ srt, int r0, int r1, int j) {
     const int t = threadIdx.x;
     int wb, we, nsub;
     wave_rows(r0, r1, t / kWave, wb, we, nsub);
-    const int r = wb + j * kWave + (t % kWave);
-    if (r >= we) return -1;
-    const int4 info = srt[r];
+    RowFetch f;
+    f.r = wb + j * kWave + (t % kWave);
+    f.pg = f.pl = -1;
+    f.info = make_int4(0, 0, 0, 0);
+    if (f.r >= we) {
+        f.r = -1;
+        return f;
+    }
+    f.info = srt[f.r];
+    if (f.r > wb) {
+        const int4 prev = srt[f.r - 1];
+        f.pg = prev.z;
+        f.pl = prev.w;
+    }
+    return f;
+}
+
+// Stage a fetched sub-chunk into LDS.  Returns the sorted row index (or -1).  Row data: the
+// policy's two words (f/c and the per-brick reference phase for COMP32) and the packed row word.
+template <int MODE>
+__device__ __forceinline__ int stage_fetched(const Geo &g, const TileSmem &sm, const RowFetch &f) {
+    if (f.r < 0) return -1;
+    const int4 info = f.info;
     const float2 rd = Phase<MODE>::row_data(sm, g.kappa[info.y], ant_of_g(g, info.z), ant_of_l(g, info.w));
     int word = info.z | (info.w << 12);
-    if (r == wb) {
-        word |= kNewG | kNewPair;
-    } else {
-        const int4 prev = srt[r - 1];
-        if (prev.z != info.z) word |= kNewG | kNewPair;
-        else if (prev.w != info.w) word |= kNewPair;
-    }
-    sm.rowinfo[t] = make_float4(rd.x, rd.y, __int_as_float(word), 0.f);
-    return r;
+    if (f.pg != info.z) word |= kNewG | kNewPair;  // also the first row of the run (pg = -1)
+    else if (f.pl != info.w) word |= kNewPair;
+    sm.rowinfo[threadIdx.x] = make_float4(rd.x, rd.y, __int_as_float(word), 0.f);
+    return f.r;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -492,10 +511,12 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
     wave_rows(r0, r1, wave, wb, we, nsub);
     const float4 *rinfo = sm.rowinfo + wave * kWave;
 
+    RowFetch next = fetch_rows(srt, r0, r1, 0);
     for (int j = 0; j < nsub; ++j) {
         __syncthreads();  // previous sub-chunk fully consumed; L-side staged
-        const int my_row = stage_rows<MODE>(g, sm, srt, r0, r1, j);
+        const int my_row = stage_fetched<MODE>(g, sm, next);
         __syncthreads();
+        if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         // Blocks of up to 16 rows that share the G antenna; one transposed reduction per block.
         for (int i0 = 0; i0 < cnt;) {
@@ -691,9 +712,10 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
     wave_rows(r0, r1, wave, wb, we, nsub);
     const float4 *rinfo = sm.rowinfo + wave * kWave;
 
+    RowFetch next = fetch_rows(srt, r0, r1, 0);
     for (int j = 0; j < nsub; ++j) {
         __syncthreads();
-        const int my_row = stage_rows<MODE>(g, sm, srt, r0, r1, j);
+        const int my_row = stage_fetched<MODE>(g, sm, next);
         // Row data for the loop: (policy words, residual) in one LDS entry per row; the row word
         // stays in this lane's register and the pair changes of the sub-chunk become a scalar bit
         // mask, so the per-row branch waits for no LDS read.
@@ -708,6 +730,7 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
         }
         const unsigned long long pairs = __ballot(my_word & kNewPair);
         __syncthreads();
+        if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         for (int i = 0; i < cnt; ++i) {
             const float4 ri = rinfo[i];
