@@ -186,6 +186,9 @@ def main():
         plan.spgm_plan_timing(False)
     assert plan.spgm_plan_status() == 0
     dt = t1 - t0
+    # reconstruction quality of the K-step solve from zero (both branches leave it in s)
+    s_fin = s.cpu().numpy().astype(np.complex128)
+    nmse_truth_db = float(10.0 * np.log10(np.sum(np.abs(s_fin - s_true) ** 2) / np.sum(np.abs(s_true) ** 2)))
     log("timed %d steps in %.4f s (%.4f ms/step); forward tile %.4f ms avg over %d, adjoint tile %.4f ms avg over %d" % (
         K, dt, 1e3 * dt / K, fwd_ms / max(fwd_n, 1), fwd_n, adj_ms / max(adj_n, 1), adj_n))
 
@@ -245,6 +248,7 @@ def main():
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if rel_vs_oracle is None else float("%.3e" % rel_vs_oracle),
         "rel_l2_vs_oracle_after_iters": n_par,
+        "nmse_db_vs_truth_after_steps": round(nmse_truth_db, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
