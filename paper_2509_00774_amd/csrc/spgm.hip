@@ -608,18 +608,34 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__rest
 // 3. Row reduction: v_i = q_f * sum_tiles part[tile][i]  (minus y_m when y is given).
 //    out_user[j] = v (caller order); out_scaled[i] = conj(q_f) * v (sorted order, adjoint input).
 // ------------------------------------------------------------------------------------------
-constexpr int kRedGroups = 16;  // tile groups per row-reduction work-group (64 rows x 16)
+constexpr int kRedGroups = 16;  // tile groups per row-reduction work-group (ROWS rows x 16)
+constexpr int kRedRows = 16;    // rows per work-group of the single-plan reduction
 
+// ROWS rows per work-group of ROWS * kRedGroups threads; thread group k sums the tiles
+// t = k mod kRedGroups and the groups are combined in order, whatever ROWS is.
+template <int ROWS>
 __device__ __forceinline__ void row_reduce_body(const Geo &g, const float2 *__restrict__ part, int n_tiles, int B,
                                                 const int4 *__restrict__ srt, const int32_t *__restrict__ rows,
                                                 const float2 *__restrict__ y, float2 *__restrict__ out_user,
                                                 float2 *__restrict__ out_scaled, int row0) {
-    __shared__ float2 red[kRedGroups][64];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    __shared__ float2 red[kRedGroups][ROWS];
+    const int tx = threadIdx.x % ROWS, ty = threadIdx.x / ROWS;
     const int i = row0 + tx;
     float ar = 0.f, ai = 0.f;
     if (i < B) {
-        for (int t = ty; t < n_tiles; t += kRedGroups) {
+        // eight loads in flight, then the additions in tile order
+        int t = ty;
+        for (; t + 7 * kRedGroups < n_tiles; t += 8 * kRedGroups) {
+            float2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(t + u * kRedGroups) * B + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                ar += v[u].x;
+                ai += v[u].y;
+            }
+        }
+        for (; t < n_tiles; t += kRedGroups) {
             const float2 v = part[(size_t)t * B + i];
             ar += v.x;
             ai += v.y;
@@ -651,13 +667,15 @@ __device__ __forceinline__ void row_reduce_body(const Geo &g, const float2 *__re
     }
 }
 
-__global__ __launch_bounds__(64 * kRedGroups) void k_row_reduce(Geo g, const float2 *__restrict__ part, int n_tiles,
-                                                               int B, const int4 *__restrict__ srt,
-                                                               const int32_t *__restrict__ rows,
-                                                               const float2 *__restrict__ y,
-                                                               float2 *__restrict__ out_user,
-                                                               float2 *__restrict__ out_scaled) {
-    row_reduce_body(g, part, n_tiles, B, srt, rows, y, out_user, out_scaled, blockIdx.x * 64);
+// Few rows per work-group, so that even a few thousand rows spread over every compute unit.
+__global__ __launch_bounds__(kRedRows * kRedGroups) void k_row_reduce(Geo g, const float2 *__restrict__ part,
+                                                                     int n_tiles, int B,
+                                                                     const int4 *__restrict__ srt,
+                                                                     const int32_t *__restrict__ rows,
+                                                                     const float2 *__restrict__ y,
+                                                                     float2 *__restrict__ out_user,
+                                                                     float2 *__restrict__ out_scaled) {
+    row_reduce_body<kRedRows>(g, part, n_tiles, B, srt, rows, y, out_user, out_scaled, blockIdx.x * kRedRows);
 }
 
 // Adjoint input for a caller-supplied residual: out_scaled[i] = conj(q_f) * r[j_i].
@@ -816,7 +834,18 @@ __device__ __forceinline__ void col_reduce_body(const float2 *__restrict__ gpart
                                                 float alpha, int n) {
     if (n >= N) return;
     float gr = 0.f, gi = 0.f;
-    for (int k = 0; k < nsplit; ++k) {
+    int k = 0;
+    for (; k + 3 < nsplit; k += 4) {  // four loads in flight, then the additions in order
+        float2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = gpart[(size_t)(k + u) * N + n];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            gr += v[u].x;
+            gi += v[u].y;
+        }
+    }
+    for (; k < nsplit; ++k) {
         const float2 v = gpart[(size_t)k * N + n];
         gr += v.x;
         gi += v.y;
@@ -906,7 +935,7 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_row_reduce_scenes(const Sce
                                                                       const int2 *__restrict__ blocks, int iter) {
     const int2 b = blocks[blockIdx.x];
     const SceneDev &d = sc[b.x];
-    row_reduce_body(d.geo, d.part, d.n_tiles, d.B, d.srt, d.rows + (size_t)iter * d.B, d.y, nullptr, d.rs, b.y);
+    row_reduce_body<64>(d.geo, d.part, d.n_tiles, d.B, d.srt, d.rows + (size_t)iter * d.B, d.y, nullptr, d.rs, b.y);
 }
 
 // blocks[b] = (scene, first voxel) of 256-voxel blocks: gradient step and threshold
@@ -1269,8 +1298,8 @@ int run_adjoint_partials(spgm_plan *p, const int4 *srt, int B, hipStream_t st) {
 
 int run_row_reduce(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const float2 *y, float2 *out_user,
                    float2 *out_scaled, hipStream_t st) {
-    k_row_reduce<<<(B + 63) / 64, 64 * kRedGroups, 0, st>>>(p->geo, p->d_part, p->n_tiles, B, srt, rows, y, out_user,
-                                                            out_scaled);
+    k_row_reduce<<<(B + kRedRows - 1) / kRedRows, kRedRows * kRedGroups, 0, st>>>(p->geo, p->d_part, p->n_tiles, B,
+                                                                                  srt, rows, y, out_user, out_scaled);
     return launch_check("row reduce");
 }
 
