@@ -408,6 +408,11 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int
     }
 }
 
+// Order a wave's own LDS accesses across this point.  A wave's LDS instructions execute in
+// issue order, so data written by one lane is seen by later reads of any lane of the same wave;
+// only the compiler has to be kept from moving accesses across (no work-group barrier needed).
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
+
 // Each wave owns a contiguous run of the work-group's sorted rows [r0, r1): wave w takes
 // [wb, we), a multiple of 64 rows long, so antenna changes stay as rare as in the sorted order.
 __device__ __forceinline__ void wave_rows(int r0, int r1, int w, int &wb, int &we, int &nsub) {
@@ -511,11 +516,14 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
     wave_rows(r0, r1, wave, wb, we, nsub);
     const float4 *rinfo = sm.rowinfo + wave * kWave;
 
+    // Every wave stages, reads and stores only its own rows, so after the brick tables are
+    // staged the waves run their row loops independently (no work-group barrier per sub-chunk).
     RowFetch next = fetch_rows(srt, r0, r1, 0);
+    __syncthreads();  // brick tables staged
     for (int j = 0; j < nsub; ++j) {
-        __syncthreads();  // previous sub-chunk fully consumed; L-side staged
+        wave_lds_order();  // previous sub-chunk's row data consumed
         const int my_row = stage_fetched<MODE>(g, sm, next);
-        __syncthreads();
+        wave_lds_order();
         if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         // Blocks of up to 16 rows that share the G antenna; one transposed reduction per block.
@@ -591,7 +599,7 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
             if ((lane & 3) == 0 && row < len) sm.rowv[wave * kWave + i0 + row] = make_float2(tr, ti);
             i0 += len;
         }
-        __syncthreads();
+        wave_lds_order();
         if (my_row >= 0) part[(size_t)tile * B + my_row] = sm.rowv[threadIdx.x];
     }
 }
@@ -731,8 +739,9 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
     const float4 *rinfo = sm.rowinfo + wave * kWave;
 
     RowFetch next = fetch_rows(srt, r0, r1, 0);
+    __syncthreads();  // brick tables staged; from here each wave works on its own rows only
     for (int j = 0; j < nsub; ++j) {
-        __syncthreads();
+        wave_lds_order();  // previous sub-chunk's row data consumed
         const int my_row = stage_fetched<MODE>(g, sm, next);
         // Row data for the loop: (policy words, residual) in one LDS entry per row; the row word
         // stays in this lane's register and the pair changes of the sub-chunk become a scalar bit
@@ -747,7 +756,7 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
             sm.rowinfo[threadIdx.x] = e;
         }
         const unsigned long long pairs = __ballot(my_word & kNewPair);
-        __syncthreads();
+        wave_lds_order();
         if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         for (int i = 0; i < cnt; ++i) {
