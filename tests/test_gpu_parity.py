@@ -81,6 +81,9 @@ def test_c0_projector(bd):
     (9, 3, 4, (8, 8, 4), 1),        # a single row
     (6, 6, 3, (17, 9, 5), 108),     # every row of the matrix
     (2, 1, 1, (3, 2, 1), 2),        # smallest grid, one brick mostly empty
+    (64, 64, 2, (8, 8, 4), 500),    # largest smaller array (64 antennas staged per brick)
+    (448, 64, 1, (9, 8, 4), 300),   # largest antenna count (T + R = 512)
+    (16, 16, 80, (8, 8, 4), 20000),  # minibatch longer than one sort chunk (16384 rows)
 ])
 def test_ragged_shapes(bd, T, R, F, grid, B):
     pulse = np.exp(1j * np.linspace(0, 2, F)) * np.linspace(1.0, 0.4, F)
