@@ -259,6 +259,23 @@ def main():
             1e3 * r["runtime_s"], fmt(r.get("speedup_vs_pgm"), "%.2f"), fmt(r["psnr_db_vs_pgm"], "%.2f"),
             fmt(r["psnr_db_vs_pgm_converged"], "%.2f"), fmt(r["nmse_db_vs_truth"], "%.2f"),
             fmt(ms(r["runtime_s_to_30db_vs_converged"]), "%.1f"), fmt(ms(r["runtime_s_to_40db_vs_converged"]), "%.1f")))
+    # Convergence against time (the counterpart of Fig. 3): PSNR against the converged PGM
+    # reconstruction at fixed runtimes, from each run's recorded curve.
+    marks_ms = (10, 25, 50, 100, 200, 400, 800, 1600)
+    lines += ["", "PSNR (dB) against the converged PGM reconstruction after a given runtime:", "",
+              "| run | " + " | ".join("%d ms" % m for m in marks_ms) + " |",
+              "|---|" + "---|" * len(marks_ms)]
+    for name, r in records.items():
+        curve = r["curve"]
+        if not curve or curve[0][2] is None:
+            continue
+        cells = []
+        for m in marks_ms:
+            k = int(m * 1e-3 / r["s_per_iteration"])
+            pts = [c for c in curve if c[0] <= k]
+            v = pts[-1][2] if pts else None
+            cells.append("—" if v is None or not np.isfinite(v) or k > r["iterations"] else "%.1f" % v)
+        lines.append("| %s | %s |" % (name, " | ".join(cells)))
     open(args.out + "_table.md", "w").write("\n".join(lines) + "\n")
     print("\n".join(lines), flush=True)
 
