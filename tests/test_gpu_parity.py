@@ -191,6 +191,32 @@ def test_c1_full_size_sampled(bd):
     check(g_gpu[vs], orc.adjoint_voxels(rows, r.astype(np.complex128), vs), "c1 adjoint (96 sampled voxels)")
 
 
+def test_c1_twenty_iterations(bd):
+    """The first 20 SPGM iterations of the c1 workload at full size (B = 4096 rows of M = 65 536,
+    N = 131 072 voxels, the benchmark's step size and threshold) against the FP64 oracle, from
+    measurements the oracle forms from the sparse c1 scene (about a minute of oracle time)."""
+    import json
+    import os
+    cfg = W.CONFIGS["c1"]
+    geom = W.config_geometry("c1")
+    orc = Oracle(geom)
+    plan = bd.Plan(geom)
+    sj = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "step_sizes.json")))["c1"]
+    eta = float(np.float32(sj["eta"]))
+    alpha = float(np.float32(sj["lambda"] * eta))
+    s_true, idx = W.config_scene("c1")
+    y = W.add_noise(orc.forward_sparse(np.arange(orc.M), idx, s_true[idx]), cfg["snr_db"], seed=cfg["seed"] + 2)
+    y = y.astype(np.complex64).astype(np.complex128)
+    rows = W.config_rows("c1", K=20)
+    s_gpu = torch.zeros(orc.N, dtype=torch.complex64, device="cuda")
+    plan.solve(idev(rows), cdev(y), s_gpu, eta, alpha)
+    got = host(s_gpu)
+    ref = orc.solve(rows, y, np.zeros(orc.N), eta, alpha)
+    say("c1 20 iterations: nnz gpu %d oracle %d" % (np.count_nonzero(got), np.count_nonzero(ref)))
+    check(got, ref, "c1 solve K=20")
+    assert plan.status() == 0
+
+
 # ---------------------------------------------------------------------------------------
 # Phase-precision variants.  Stated tolerances (relative L2 against the FP64 oracle):
 #   float64 distance and phase   <= 1e-6
