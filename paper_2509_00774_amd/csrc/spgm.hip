@@ -75,6 +75,10 @@ struct Geo {
     int nG, nL;
     double cx, cy, cz;    // grid centre
     double px, py, pz;    // pitch
+    // Precomputed L-side tables of the plan's phase policy, [brick][nL][256] entries of 8 bytes
+    // (nullptr: every work-group forms its brick's table itself); ltab_mode names the policy.
+    const float4 *ltab;
+    int ltab_mode;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -387,13 +391,24 @@ template <> struct Phase<SPGM_PHASE_NAIVE32> {
     static __device__ float phase(float4 ri, D d) { return __builtin_amdgcn_fractf(ri.x * d); }
 };
 
-template <int MODE>
+// Antenna terms of brick (bx, by, bz) and its L-side table in LDS.  With a precomputed table
+// for this policy the brick's entries are copied (16-byte loads) instead of formed; either way
+// the caller synchronises the work-group before reading them.
+template <int MODE, bool TABLE = true>
 __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int bx, int by, int bz) {
     using P = Phase<MODE>;
+    static_assert(sizeof(typename P::LE) == 8, "L-side entries are 8 bytes");
     double cx, cy, cz;
     brick_centre(g, bx, by, bz, cx, cy, cz);
     const int A = g.T + g.R;
     for (int a = threadIdx.x; a < A; a += kThreads) P::stage_ant(g, sm, a, cx, cy, cz);
+    if (TABLE && g.ltab && g.ltab_mode == MODE) {
+        const int n4 = g.nL * (kBrick / 2);  // float4 per brick table
+        const float4 *src = g.ltab + (size_t)((bz * g.nby + by) * g.nbx + bx) * n4;
+        float4 *dst = static_cast<float4 *>(sm.lside);
+        for (int i = threadIdx.x; i < n4; i += kThreads) dst[i] = src[i];
+        return;
+    }
     __syncthreads();
     const int v = threadIdx.x % kBrick;  // brick voxel: lane -> (x, y), (wave mod 4) -> z
     const int lx = (v & 63) & 7, ly = (v & 63) >> 3, lz = v >> 6;
@@ -406,6 +421,21 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int
         if (inside) P::geom(sm, ant_of_l(g, li), vx, dl, wl);
         lside[li * kBrick + v] = P::lentry(dl, wl);  // voxels outside the grid contribute 0
     }
+}
+
+// Forms the L-side table of brick blockIdx.x with the same code as stage_tile and stores it.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_build_ltab(Geo g, float4 *__restrict__ tab) {
+    extern __shared__ __align__(16) char smem[];
+    const TileSmem sm = carve(smem, g);
+    int bx, by, bz;
+    brick_of(g, blockIdx.x, bx, by, bz);
+    stage_tile<MODE, false>(g, sm, bx, by, bz);
+    __syncthreads();
+    const int n4 = g.nL * (kBrick / 2);
+    const float4 *src = static_cast<const float4 *>(sm.lside);
+    float4 *dst = tab + (size_t)blockIdx.x * n4;
+    for (int i = threadIdx.x; i < n4; i += kThreads) dst[i] = src[i];
 }
 
 // Order a wave's own LDS accesses across this point.  A wave's LDS instructions execute in
@@ -1090,6 +1120,7 @@ struct spgm_plan {
     double *d_kappa = nullptr;
     float2 *d_q = nullptr;
     int *d_status = nullptr;
+    float4 *d_ltab = nullptr;  // precomputed L-side tables (geo.ltab), when they fit
     // workspace, sized for ws_B rows and ws_splits row ranges
     int ws_B = 0;
     int ws_splits = 0;
@@ -1661,6 +1692,44 @@ extern "C" {
 
 const char *spgm_last_error(void) { return g_last_error.c_str(); }
 
+// L-side tables of every brick (geometry only), formed once per plan with the same code the tile
+// kernels would run and then copied by them instead of formed by every work-group.  Skipped
+// (the kernels form the tables themselves) when they would exceed kMaxLtabBytes or cannot be
+// allocated; the results are the same either way, bit for bit.
+static constexpr size_t kMaxLtabBytes = size_t(8) << 30;
+
+static void build_ltab(spgm_plan *p) {
+    Geo &g = p->geo;
+    const size_t bytes = sizeof(float2) * kBrick * (size_t)g.nL * (size_t)p->n_tiles;
+    if (bytes > kMaxLtabBytes || hipMalloc(&p->d_ltab, bytes) != hipSuccess) {
+        p->d_ltab = nullptr;
+        hipGetLastError();
+        return;
+    }
+    const void *fn = p->phase_mode == SPGM_PHASE_F64       ? (const void *)k_build_ltab<SPGM_PHASE_F64>
+                     : p->phase_mode == SPGM_PHASE_NAIVE32 ? (const void *)k_build_ltab<SPGM_PHASE_NAIVE32>
+                                                           : (const void *)k_build_ltab<SPGM_PHASE_COMP32>;
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
+    switch (p->phase_mode) {
+    case SPGM_PHASE_F64:
+        k_build_ltab<SPGM_PHASE_F64><<<p->n_tiles, kThreads, p->lds_bytes>>>(g, p->d_ltab);
+        break;
+    case SPGM_PHASE_NAIVE32:
+        k_build_ltab<SPGM_PHASE_NAIVE32><<<p->n_tiles, kThreads, p->lds_bytes>>>(g, p->d_ltab);
+        break;
+    default:
+        k_build_ltab<SPGM_PHASE_COMP32><<<p->n_tiles, kThreads, p->lds_bytes>>>(g, p->d_ltab);
+    }
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipGetLastError();
+        hipFree(p->d_ltab);
+        p->d_ltab = nullptr;
+        return;
+    }
+    g.ltab = p->d_ltab;
+    g.ltab_mode = p->phase_mode;
+}
+
 int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mode) {
     if (!out) return fail(SPGM_E_INVALID, "spgm_plan_create: out is NULL");
     *out = nullptr;
@@ -1798,6 +1867,7 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     hipFuncSetAttribute((const void *)k_sf_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
     hipFuncSetAttribute((const void *)k_sf_adj, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
     hipGetLastError();
+    build_ltab(p);
     *out = p;
     return ok();
 }
@@ -1810,6 +1880,7 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_kappa);
     hipFree(p->d_q);
     hipFree(p->d_status);
+    hipFree(p->d_ltab);
     hipFree(p->d_srt);
     hipFree(p->d_part);
     hipFree(p->d_rs);
