@@ -443,6 +443,24 @@ __global__ __launch_bounds__(kThreads) void k_build_ltab(Geo g, float4 *__restri
 // only the compiler has to be kept from moving accesses across (no work-group barrier needed).
 __device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
 
+// Brick and row split of a tile work-group on a (bricks, splits) grid.  Work-groups go to the
+// eight XCDs round-robin in linear launch order; when the brick count is a multiple of eight,
+// consecutive work-groups on one XCD take the row splits of one brick, so the splits read that
+// brick's L-side table and source values through the same L2 at about the same time instead of
+// once per split from the fabric.  Otherwise the grid coordinates are used directly.
+__device__ __forceinline__ void tile_and_split(int &tile, int &split) {
+    const int nt = gridDim.x, ns = gridDim.y;
+    if ((nt & 7) != 0) {
+        tile = blockIdx.x;
+        split = blockIdx.y;
+        return;
+    }
+    const int lin = blockIdx.y * nt + blockIdx.x;
+    const int slot = lin >> 3, q = slot / ns;
+    tile = (lin & 7) + 8 * q;
+    split = slot - q * ns;
+}
+
 // Each wave owns a contiguous run of the work-group's sorted rows [r0, r1): wave w takes
 // [wb, we), a multiple of 64 rows long, so antenna changes stay as rare as in the sorted order.
 __device__ __forceinline__ void wave_rows(int r0, int r1, int w, int &wb, int &we, int &nsub) {
@@ -638,8 +656,10 @@ template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
                                                        const float2 *__restrict__ s, float2 *__restrict__ part) {
     extern __shared__ __align__(16) char smem[];
-    const int r0 = blockIdx.y * rows_per_wg;
-    fwd_tile_body<MODE>(g, smem, blockIdx.x, r0, min(B, r0 + rows_per_wg), srt, B, s, part);
+    int tile, split;
+    tile_and_split(tile, split);
+    const int r0 = split * rows_per_wg;
+    fwd_tile_body<MODE>(g, smem, tile, r0, min(B, r0 + rows_per_wg), srt, B, s, part);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -861,8 +881,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
                                                        const float2 *__restrict__ rs, float2 *__restrict__ gpart,
                                                        int N) {
     extern __shared__ __align__(16) char smem[];
-    const int r0 = blockIdx.y * rows_per_wg;
-    adj_tile_body<MODE>(g, smem, blockIdx.x, blockIdx.y, r0, min(B, r0 + rows_per_wg), srt, B, rs, gpart, N);
+    int tile, split;
+    tile_and_split(tile, split);
+    const int r0 = split * rows_per_wg;
+    adj_tile_body<MODE>(g, smem, tile, split, r0, min(B, r0 + rows_per_wg), srt, B, rs, gpart, N);
 }
 
 // ------------------------------------------------------------------------------------------
