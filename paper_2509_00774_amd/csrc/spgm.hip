@@ -574,78 +574,77 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
         wave_lds_order();
         if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
-        // Blocks of up to 16 rows that share the G antenna; one transposed reduction per block.
-        for (int i0 = 0; i0 < cnt;) {
-            const int w0 = uniform(__float_as_int(rinfo[i0].z));
-            if (w0 & kNewG) {
-                const int ga = ant_of_g(g, row_g(w0));
-#pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    DT dg;
-                    float wg;
-                    P::geom(sm, ga, vox[p], dg, wg);
-                    dG[p] = valid[p] ? dg : DT(0);
-                    usr[p] = valid[p] ? wg * sr[p] : 0.f;
-                    usi[p] = valid[p] ? wg * si[p] : 0.f;
-                }
-            }
-            // block length: rows i0 .. i0+len-1 all use the same G antenna
+        // Blocks of 16 consecutive rows, one transposed reduction each.  G-antenna and pair changes
+        // are handled at the row where they happen.  Rows of the last block past cnt are formed
+        // from stale entries of this wave's row buffer (i0 + 15 < 64) and discarded: the
+        // transposed reduction never mixes rows, and their flags are masked off, so they change
+        // no state.
+        for (int i0 = 0; i0 < cnt; i0 += 16) {
+            const int len = min(16, cnt - i0);
             const int q = lane & 15;
-            const int iq = i0 + q;
-            const int wq = __float_as_int(rinfo[min(iq, cnt - 1)].z);  // lane q: word of row i0 + q
-            const bool stop = iq >= cnt || (q > 0 && (wq & kNewG));
-            const unsigned long long stops = __ballot(stop) & 0xffffull;
-            const int len = stops ? __ffsll((long long)stops) - 1 : 16;
+            const int wq = __float_as_int(rinfo[i0 + min(q, len - 1)].z);  // lane q: word of row i0 + q
             // pair changes of the block as a scalar bit mask: the per-row branch needs no lane read
-            const unsigned long long pairs = __ballot(wq & kNewPair) & 0xffffull;
+            const unsigned long long live = len == 16 ? 0xffffull : (1ull << len) - 1;
+            const unsigned long long pairs = __ballot(wq & kNewPair) & live;
+            // The block's row entries are read through one address register with immediate
+            // offsets: an opaque zero keeps the base in a VGPR instead of re-forming it per row.
+            int zero;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+            const float4 *rblk = rinfo + i0 + zero;
 #pragma unroll
             for (int qq = 0; qq < 16; ++qq) {
-                if (qq < len) {
-                    const float4 ri = rinfo[i0 + qq];
-                    if ((pairs >> qq) & 1ull) {
-                        const int word = __builtin_amdgcn_readlane(wq, qq);
-                        const typename P::LE *lp = lbase + row_l(word) * kBrick;
+                const float4 ri = rblk[qq];
+                if ((pairs >> qq) & 1ull) {
+                    const int word = __builtin_amdgcn_readlane(wq, qq);
+                    if (word & kNewG) {  // a new G antenna also starts a new pair
+                        const int ga = ant_of_g(g, row_g(word));
 #pragma unroll
                         for (int p = 0; p < kP; ++p) {
-                            const typename P::LE lv = lp[p * kWave];
-                            const float wl = P::lw(lv);
-                            D[p] = P::pair_d(dG[p], lv);
-                            ur[p] = wl * usr[p];
-                            ui[p] = wl * usi[p];
+                            DT dg;
+                            float wg;
+                            P::geom(sm, ga, vox[p], dg, wg);
+                            dG[p] = valid[p] ? dg : DT(0);
+                            usr[p] = valid[p] ? wg * sr[p] : 0.f;
+                            usi[p] = valid[p] ? wg * si[p] : 0.f;
                         }
                     }
-                    float ar, ai;
+                    const typename P::LE *lp = lbase + row_l(word) * kBrick;
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
-                        const float ph = P::phase(ri, D[p]);
-                        const float sn = __builtin_amdgcn_sinf(ph);
-                        const float cs = __builtin_amdgcn_cosf(ph);
-                        // (cs - j sn)(ur + j ui)
-                        if (p == 0) {
-                            ar = cs * ur[p];
-                            ai = cs * ui[p];
-                        } else {
-                            ar = fmaf(cs, ur[p], ar);
-                            ai = fmaf(cs, ui[p], ai);
-                        }
-                        ar = fmaf(sn, ui[p], ar);
-                        ai = fmaf(-sn, ur[p], ai);
+                        const typename P::LE lv = lp[p * kWave];
+                        const float wl = P::lw(lv);
+                        D[p] = P::pair_d(dG[p], lv);
+                        ur[p] = wl * usr[p];
+                        ui[p] = wl * usi[p];
                     }
-                    accr[qq] = ar;
-                    acci[qq] = ai;
-                } else {
-                    // defined values for the rows past the block end (their sums are discarded),
-                    // so that no accumulator stays live across the reduction and the lane swaps
-                    // below can work in place
-                    accr[qq] = 0.f;
-                    acci[qq] = 0.f;
                 }
+                float ar, ai;
+#pragma unroll
+                for (int p = 0; p < kP; ++p) {
+                    const float ph = P::phase(ri, D[p]);
+                    const float sn = __builtin_amdgcn_sinf(ph);
+                    const float cs = __builtin_amdgcn_cosf(ph);
+                    // (cs - j sn)(ur + j ui)
+                    if (p == 0) {
+                        ar = cs * ur[p];
+                        ai = cs * ui[p];
+                    } else {
+                        ar = fmaf(cs, ur[p], ar);
+                        ai = fmaf(cs, ui[p], ai);
+                    }
+                    ar = fmaf(sn, ui[p], ar);
+                    ai = fmaf(-sn, ur[p], ai);
+                }
+                // the row's sums are formed here, not sunk to the reduction (which would keep every
+                // row's pair terms live at once)
+                asm volatile("" : "+v"(ar), "+v"(ai));
+                accr[qq] = ar;
+                acci[qq] = ai;
             }
             const float tr = wave_transpose_sum16(accr, b3, b2);
             const float ti = wave_transpose_sum16(acci, b3, b2);
             const int row = lane >> 2;
             if ((lane & 3) == 0 && row < len) sm.rowv[wave * kWave + i0 + row] = make_float2(tr, ti);
-            i0 += len;
         }
         wave_lds_order();
         if (my_row >= 0) part[(size_t)tile * B + my_row] = sm.rowv[threadIdx.x];
@@ -804,52 +803,63 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
             e.z = rv.x;
             e.w = rv.y;
             sm.rowinfo[threadIdx.x] = e;
+        } else {
+            // rows past the run: zero residual and phase words, so they add exactly nothing
+            sm.rowinfo[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         const unsigned long long pairs = __ballot(my_word & kNewPair);
         wave_lds_order();
         if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
-        for (int i = 0; i < cnt; ++i) {
-            const float4 ri = rinfo[i];
-            const float2 rv = make_float2(ri.z, ri.w);
-            if ((pairs >> i) & 1ull) {
-                const int word = __builtin_amdgcn_readlane(my_word, i);
-                // close the previous pair and set up the new one
+        // Blocks of 16 rows, unrolled: row entries through one address register with immediate
+        // offsets (an opaque zero keeps the base in a VGPR).
+        int zero;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+        const float4 *rsub = rinfo + zero;
+        for (int i0 = 0; i0 < cnt; i0 += 16) {
 #pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    gr[p] = fmaf(W[p], hr[p], gr[p]);
-                    gi_[p] = fmaf(W[p], hi[p], gi_[p]);
-                    hr[p] = hi[p] = 0.f;
-                }
-                if (word & kNewG) {
-                    const int ga = ant_of_g(g, row_g(word));
+            for (int qq = 0; qq < 16; ++qq) {
+                const float4 ri = rsub[i0 + qq];
+                const float2 rv = make_float2(ri.z, ri.w);
+                if ((pairs >> (i0 + qq)) & 1ull) {
+                    const int word = __builtin_amdgcn_readlane(my_word, i0 + qq);
+                    // close the previous pair and set up the new one
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
-                        DT dg;
-                        float wg;
-                        P::geom(sm, ga, vox[p], dg, wg);
-                        dG[p] = valid[p] ? dg : DT(0);
-                        wG[p] = valid[p] ? wg : 0.f;
+                        gr[p] = fmaf(W[p], hr[p], gr[p]);
+                        gi_[p] = fmaf(W[p], hi[p], gi_[p]);
+                        hr[p] = hi[p] = 0.f;
+                    }
+                    if (word & kNewG) {
+                        const int ga = ant_of_g(g, row_g(word));
+#pragma unroll
+                        for (int p = 0; p < kP; ++p) {
+                            DT dg;
+                            float wg;
+                            P::geom(sm, ga, vox[p], dg, wg);
+                            dG[p] = valid[p] ? dg : DT(0);
+                            wG[p] = valid[p] ? wg : 0.f;
+                        }
+                    }
+                    const typename P::LE *lp = lbase + row_l(word) * kBrick;
+#pragma unroll
+                    for (int p = 0; p < kP; ++p) {
+                        const typename P::LE lv = lp[p * kWave];
+                        D[p] = P::pair_d(dG[p], lv);
+                        W[p] = wG[p] * P::lw(lv);
                     }
                 }
-                const typename P::LE *lp = lbase + row_l(word) * kBrick;
 #pragma unroll
                 for (int p = 0; p < kP; ++p) {
-                    const typename P::LE lv = lp[p * kWave];
-                    D[p] = P::pair_d(dG[p], lv);
-                    W[p] = wG[p] * P::lw(lv);
+                    const float ph = P::phase(ri, D[p]);
+                    const float sn = __builtin_amdgcn_sinf(ph);
+                    const float cs = __builtin_amdgcn_cosf(ph);
+                    // (cs + j sn)(rv.x + j rv.y)
+                    hr[p] = fmaf(cs, rv.x, hr[p]);
+                    hr[p] = fmaf(-sn, rv.y, hr[p]);
+                    hi[p] = fmaf(cs, rv.y, hi[p]);
+                    hi[p] = fmaf(sn, rv.x, hi[p]);
                 }
-            }
-#pragma unroll
-            for (int p = 0; p < kP; ++p) {
-                const float ph = P::phase(ri, D[p]);
-                const float sn = __builtin_amdgcn_sinf(ph);
-                const float cs = __builtin_amdgcn_cosf(ph);
-                // (cs + j sn)(rv.x + j rv.y)
-                hr[p] = fmaf(cs, rv.x, hr[p]);
-                hr[p] = fmaf(-sn, rv.y, hr[p]);
-                hi[p] = fmaf(cs, rv.y, hi[p]);
-                hi[p] = fmaf(sn, rv.x, hi[p]);
             }
         }
     }
@@ -965,9 +975,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scenes(const SceneDev *__
     sort_rows_body(d.geo, keys, d.rows + (size_t)iter * d.B, d.B, d.srt, status, blockIdx.x);
 }
 
+// At most 128 VGPRs (four waves per SIMD): two work-groups per CU, as the LDS allows.
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_fwd_items(const SceneDev *__restrict__ sc, const int4 *__restrict__ items,
-                                                        int n_items) {
+__global__ __launch_bounds__(kThreads, 4) void k_fwd_items(const SceneDev *__restrict__ sc,
+                                                           const int4 *__restrict__ items, int n_items) {
     extern __shared__ __align__(16) char smem[];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 w = uniform4(items[it]);  // (scene, brick, split, cost)
