@@ -91,8 +91,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the projector on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of the build).", file=sys.stderr)
+        print("bench.py measures one GPU only: the projector runs on a single MI355X; "
+              "runs over several GPUs are not supported.", file=sys.stderr)
         sys.exit(2)
 
     import torch
