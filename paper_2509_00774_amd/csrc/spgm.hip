@@ -1689,11 +1689,20 @@ int sf_prepare(spgm_plan *p, const SFArgs &a, hipStream_t st) {
     return launch_check("structured rows");
 }
 
+// Subsets of at most 32 antennas in all, at most 16 of them transmitters, take the kernels'
+// small-register instances.
+bool sf_small(const SFArgs &a) { return a.nt + a.nr <= 32 && a.nt <= 16; }
+
 int sf_forward_partials(spgm_plan *p, const SFArgs &a, const float2 *s, hipStream_t st) {
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
     if (ev) hipEventRecord(ev[0], st);
-    k_sf_fwd<<<p->n_tiles, kThreads, sf_lds_bytes(p->geo.T + p->geo.R), st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri,
-                                                                              a.nr, s, p->d_part, a.B);
+    const size_t lds = sf_lds_bytes(p->geo.T + p->geo.R);
+    if (sf_small(a))
+        k_sf_fwd<kSFItemsSmall><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr, s,
+                                                                   p->d_part, a.B);
+    else
+        k_sf_fwd<kSFItems><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr, s,
+                                                              p->d_part, a.B);
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("structured forward");
 }
@@ -1702,8 +1711,13 @@ int sf_forward_partials(spgm_plan *p, const SFArgs &a, const float2 *s, hipStrea
 int sf_adjoint_partials(spgm_plan *p, const SFArgs &a, hipStream_t st) {
     hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
     if (ev) hipEventRecord(ev[0], st);
-    k_sf_adj<<<p->n_tiles, kThreads, sf_lds_bytes(p->geo.T + p->geo.R), st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri,
-                                                                              a.nr, p->d_rs, p->d_gpart, (int)p->N);
+    const size_t lds = sf_lds_bytes(p->geo.T + p->geo.R);
+    if (sf_small(a))
+        k_sf_adj<kSFItemsSmall, 2><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr,
+                                                                      p->d_rs, p->d_gpart, (int)p->N);
+    else
+        k_sf_adj<kSFItems, 4><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr, p->d_rs,
+                                                                 p->d_gpart, (int)p->N);
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("structured adjoint");
 }
@@ -1897,8 +1911,10 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
         (const void *)k_mm_fwd<SPGM_MM_FP16, 3>, (const void *)k_mm_fwd<SPGM_MM_FP16, 4>,
         (const void *)k_mm_adj<SPGM_MM_BF16>, (const void *)k_mm_adj<SPGM_MM_FP16>};
     for (const void *k : mm_kernels) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    hipFuncSetAttribute((const void *)k_sf_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
-    hipFuncSetAttribute((const void *)k_sf_adj, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
+    const void *sf_kernels[] = {(const void *)k_sf_fwd<kSFItemsSmall>, (const void *)k_sf_fwd<kSFItems>,
+                                (const void *)k_sf_adj<kSFItemsSmall, 2>, (const void *)k_sf_adj<kSFItems, 4>};
+    for (const void *k : sf_kernels)
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
     hipGetLastError();
     build_ltab(p);
     *out = p;
