@@ -253,6 +253,7 @@ struct TileSmem {
     double4 *antg64; // [T+R]: F64 (c - r_a, |c - r_a|) float64 (aliases antg/antd)
     float4 *rowinfo; // [kSub]: (row data x, row data y, packed row word as bits, 0)
     float2 *rowv;    // [kSub]: forward row sums / adjoint scaled residuals
+    float2 *snew;    // [kBrick]: the brick's iterate after a deferred proximal step (forward)
     void *lside;     // [nL][256]: per L antenna per brick voxel (layout set by the phase policy)
 };
 
@@ -274,7 +275,8 @@ __device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
     char *p = smem + kAntBytes * A;
     t.rowinfo = reinterpret_cast<float4 *>(p);
     t.rowv = reinterpret_cast<float2 *>(t.rowinfo + kSub);
-    t.lside = t.rowv + kSub;
+    t.snew = t.rowv + kSub;
+    t.lside = t.snew + kBrick;
     return t;
 }
 
@@ -514,6 +516,50 @@ __device__ __forceinline__ int stage_fetched(const Geo &g, const TileSmem &sm, c
     return f.r;
 }
 
+// Fixed-order sum over the row splits of the adjoint partials of voxel n (four loads in
+// flight, then the additions in order).
+__device__ __forceinline__ float2 split_sum(const float2 *__restrict__ gpart, int nsplit, int N, size_t n) {
+    float gr = 0.f, gi = 0.f;
+    int k = 0;
+    for (; k + 3 < nsplit; k += 4) {
+        float2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = gpart[(size_t)(k + u) * N + n];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            gr += v[u].x;
+            gi += v[u].y;
+        }
+    }
+    for (; k < nsplit; ++k) {
+        const float2 v = gpart[(size_t)k * N + n];
+        gr += v.x;
+        gi += v.y;
+    }
+    return make_float2(gr, gi);
+}
+
+// Gradient step and complex soft threshold of Eq. 5: S_alpha(v - step g).
+__device__ __forceinline__ float2 prox_step(float2 v, float2 g, float step, float alpha) {
+    v.x = fmaf(-step, g.x, v.x);
+    v.y = fmaf(-step, g.y, v.y);
+    const float mag = sqrtf(fmaf(v.x, v.x, v.y * v.y));
+    if (mag <= alpha) return make_float2(0.f, 0.f);
+    const float sc = 1.0f - alpha / mag;
+    return make_float2(v.x * sc, v.y * sc);
+}
+
+// The previous iteration's proximal step, deferred into the forward: the forward applies it to
+// the voxels it reads, s_k = S_alpha(s_{k-1} - step sum_splits gpart) (the column reduction's
+// arithmetic), and the work-groups of row split 0 store s_k to s_out, which must not alias the
+// s_{k-1} the other splits read.  gpart == nullptr: s is used as given.
+struct SStep {
+    const float2 *gpart;
+    float2 *s_out;
+    int nsplit, N;
+    float step, alpha;
+};
+
 // ------------------------------------------------------------------------------------------
 // 2. Forward partials: part[tile][i] = sum over brick voxels of (A_{row i, n} / q_f) s_n.
 // ------------------------------------------------------------------------------------------
@@ -521,13 +567,27 @@ __device__ __forceinline__ int stage_fetched(const Geo &g, const TileSmem &sm, c
 // work-list launch over many scenes: brick `tile`, sorted rows [r0, r1).
 template <int MODE>
 __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile, int r0, int r1,
-                                              const int4 *__restrict__ srt, int B, const float2 *__restrict__ s,
-                                              float2 *__restrict__ part) {
+                                              const int4 *__restrict__ srt, int B, const float2 *s,
+                                              float2 *__restrict__ part, const SStep &up, bool store_s) {
     using P = Phase<MODE>;
     using DT = typename P::D;
     const TileSmem sm = carve(smem, g);
     int bx, by, bz;
     brick_of(g, tile, bx, by, bz);
+    // A deferred proximal step: the first four waves form the brick's new iterate (voxel
+    // p * 64 + lane) into LDS, where the lanes read it after the barrier below.
+    const bool deferred = up.gpart != nullptr;
+    if (deferred && threadIdx.x < kBrick) {
+        const int v = threadIdx.x, ln = v & 63;
+        const int jx = bx * kBX + (ln & 7), jy = by * kBY + (ln >> 3), jz = bz * kBZ + (v >> 6);
+        float2 val = make_float2(0.f, 0.f);
+        if (jx < g.nx && jy < g.ny && jz < g.nz) {
+            const size_t n = ((size_t)jz * g.ny + jy) * g.nx + jx;
+            val = prox_step(s[n], split_sum(up.gpart, up.nsplit, up.N, n), up.step, up.alpha);
+            if (store_s) up.s_out[n] = val;
+        }
+        sm.snew[v] = val;
+    }
     stage_tile<MODE>(g, sm, bx, by, bz);
 
     const int lane = threadIdx.x & 63;
@@ -543,7 +603,7 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
         valid[p] = ix < g.nx && iy < g.ny && iz < g.nz;
         vox[p] = P::vox(g, bx, by, bz, lx, ly, p);
         float2 sv = make_float2(0.f, 0.f);
-        if (valid[p]) sv = s[((size_t)iz * g.ny + iy) * g.nx + ix];
+        if (!deferred && valid[p]) sv = s[((size_t)iz * g.ny + iy) * g.nx + ix];
         sr[p] = sv.x;
         si[p] = sv.y;
     }
@@ -567,7 +627,15 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
     // Every wave stages, reads and stores only its own rows, so after the brick tables are
     // staged the waves run their row loops independently (no work-group barrier per sub-chunk).
     RowFetch next = fetch_rows(srt, r0, r1, 0);
-    __syncthreads();  // brick tables staged
+    __syncthreads();  // brick tables (and a deferred step's iterate) staged
+    if (deferred) {
+#pragma unroll
+        for (int p = 0; p < kP; ++p) {
+            const float2 sv = sm.snew[p * kWave + lane];
+            sr[p] = sv.x;
+            si[p] = sv.y;
+        }
+    }
     for (int j = 0; j < nsub; ++j) {
         wave_lds_order();  // previous sub-chunk's row data consumed
         const int my_row = stage_fetched<MODE>(g, sm, next);
@@ -653,12 +721,12 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
-                                                       const float2 *__restrict__ s, float2 *__restrict__ part) {
+                                                       const float2 *s, float2 *__restrict__ part, SStep up) {
     extern __shared__ __align__(16) char smem[];
     int tile, split;
     tile_and_split(tile, split);
     const int r0 = split * rows_per_wg;
-    fwd_tile_body<MODE>(g, smem, tile, r0, min(B, r0 + rows_per_wg), srt, B, s, part);
+    fwd_tile_body<MODE>(g, smem, tile, r0, min(B, r0 + rows_per_wg), srt, B, s, part, up, split == 0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -901,48 +969,25 @@ __global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__rest
 // 5. Column reduction over row splits; optional gradient step and complex soft threshold.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void col_reduce_body(const float2 *__restrict__ gpart, int nsplit, int N,
-                                                float2 *__restrict__ g_out, float2 *__restrict__ s, float step,
-                                                float alpha, int n) {
+                                                float2 *__restrict__ g_out, const float2 *s_in, float2 *s_out,
+                                                float step, float alpha, int n) {
     if (n >= N) return;
-    float gr = 0.f, gi = 0.f;
-    int k = 0;
-    for (; k + 3 < nsplit; k += 4) {  // four loads in flight, then the additions in order
-        float2 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = gpart[(size_t)(k + u) * N + n];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            gr += v[u].x;
-            gi += v[u].y;
-        }
-    }
-    for (; k < nsplit; ++k) {
-        const float2 v = gpart[(size_t)k * N + n];
-        gr += v.x;
-        gi += v.y;
-    }
-    if (g_out) g_out[n] = make_float2(gr, gi);
-    if (s) {
-        float2 v = s[n];
-        v.x = fmaf(-step, gr, v.x);
-        v.y = fmaf(-step, gi, v.y);
-        const float mag = sqrtf(fmaf(v.x, v.x, v.y * v.y));
-        if (mag <= alpha) {
-            v.x = 0.f;
-            v.y = 0.f;
-        } else {
-            const float sc = 1.0f - alpha / mag;
-            v.x *= sc;
-            v.y *= sc;
-        }
-        s[n] = v;
-    }
+    const float2 gs = split_sum(gpart, nsplit, N, n);
+    if (g_out) g_out[n] = gs;
+    if (s_out) s_out[n] = prox_step(s_in[n], gs, step, alpha);
 }
 
 __global__ __launch_bounds__(256) void k_col_reduce(const float2 *__restrict__ gpart, int nsplit, int N,
                                                     float2 *__restrict__ g_out, float2 *__restrict__ s, float step,
                                                     float alpha) {
-    col_reduce_body(gpart, nsplit, N, g_out, s, step, alpha, blockIdx.x * blockDim.x + threadIdx.x);
+    col_reduce_body(gpart, nsplit, N, g_out, s, s, step, alpha, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The last step of a solve whose other steps were deferred into the forwards:
+// s_out = S_alpha(s_in - step sum_splits gpart); s_in and s_out may be the same array.
+__global__ __launch_bounds__(256) void k_col_reduce_to(const float2 *__restrict__ gpart, int nsplit, int N,
+                                                       const float2 *s_in, float2 *s_out, float step, float alpha) {
+    col_reduce_body(gpart, nsplit, N, nullptr, s_in, s_out, step, alpha, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -984,7 +1029,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwd_items(const SceneDev *__res
         const int4 w = uniform4(items[it]);  // (scene, brick, split, cost)
         const SceneDev &d = sc[w.x];
         const int r0 = w.z * d.rpw;
-        fwd_tile_body<MODE>(d.geo, smem, w.y, r0, min(d.B, r0 + d.rpw), d.srt, d.B, d.s, d.part);
+        fwd_tile_body<MODE>(d.geo, smem, w.y, r0, min(d.B, r0 + d.rpw), d.srt, d.B, d.s, d.part, SStep{}, false);
         __syncthreads();
     }
 }
@@ -1015,7 +1060,7 @@ __global__ __launch_bounds__(256) void k_col_reduce_scenes(const SceneDev *__res
                                                            const int2 *__restrict__ blocks) {
     const int2 b = blocks[blockIdx.x];
     const SceneDev &d = sc[b.x];
-    col_reduce_body(d.gpart, d.splits, d.N, nullptr, d.s, d.step, d.alpha, b.y + threadIdx.x);
+    col_reduce_body(d.gpart, d.splits, d.N, nullptr, d.s, d.s, d.step, d.alpha, b.y + threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1161,6 +1206,7 @@ struct spgm_plan {
     float2 *d_part = nullptr;    // forward partials [tile][row]
     float2 *d_rs = nullptr;      // scaled residuals, sorted order
     float2 *d_gpart = nullptr;   // adjoint partials [row range][voxel]
+    float2 *d_s_alt = nullptr;   // second iterate buffer of a solve [voxel]
     int4 *d_srt_all = nullptr;   // sorted rows of a batch of minibatches (solve)
     float2 *d_vjp = nullptr;     // unrolled backward: g, zbar, h (3 x N) and block partials
     double *d_vjp_part = nullptr;
@@ -1326,7 +1372,8 @@ hipEvent_t *timing_slot(spgm_plan *p, std::vector<hipEvent_t> &pool, size_t &use
     return &pool[2 * used++];
 }
 
-int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, hipStream_t st) {
+int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, hipStream_t st,
+                         const SStep &up = SStep{}) {
     const int splits = fwd_splits(p, B);
     const int rpw = (B + splits - 1) / splits;
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
@@ -1334,13 +1381,13 @@ int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, 
     const dim3 grid(p->n_tiles, splits);
     switch (p->phase_mode) {
     case SPGM_PHASE_F64:
-        k_fwd_tile<SPGM_PHASE_F64><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
+        k_fwd_tile<SPGM_PHASE_F64><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part, up);
         break;
     case SPGM_PHASE_NAIVE32:
-        k_fwd_tile<SPGM_PHASE_NAIVE32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
+        k_fwd_tile<SPGM_PHASE_NAIVE32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part, up);
         break;
     default:
-        k_fwd_tile<SPGM_PHASE_COMP32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part);
+        k_fwd_tile<SPGM_PHASE_COMP32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part, up);
     }
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("forward");
@@ -1890,7 +1937,7 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     g.kappa = p->d_kappa;
     g.q = p->d_q;
     const size_t A = (size_t)(T + R);
-    p->lds_bytes = kAntBytes * A + kSub * (sizeof(float4) + sizeof(float2)) +
+    p->lds_bytes = kAntBytes * A + kSub * (sizeof(float4) + sizeof(float2)) + sizeof(float2) * kBrick +
                    std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * kWaves);
     if (p->lds_bytes > (size_t)kMaxLds) {
         spgm_plan_destroy(p);
@@ -1934,6 +1981,7 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_part);
     hipFree(p->d_rs);
     hipFree(p->d_gpart);
+    hipFree(p->d_s_alt);
     hipFree(p->d_srt_all);
     hipFree(p->d_vjp);
     hipFree(p->d_tv_b);
@@ -2009,10 +2057,17 @@ int spgm_step(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, void 
     return ok();
 }
 
-// Issue the launches of an iters-iteration solve on `st` (workspace already sized).
+// Issue the launches of an iters-iteration solve on `st` (workspace already sized).  The
+// proximal step of iteration k is applied by the forward of iteration k + 1 to the voxels it
+// reads (one launch fewer per iteration, same arithmetic as the column reduction); iterates
+// alternate between s and the plan's second buffer, and the last step is a column reduction
+// into s.  Results are bitwise those of iters calls of the single step.
 static int solve_launches(spgm_plan *p, const int32_t *rows, int iters, int B, const float2 *y, float2 *s, float eta,
                           float alpha, hipStream_t st) {
     int rc;
+    float2 *const buf[2] = {s, p->d_s_alt};
+    const float step = eta / (float)B;
+    const int nsplit = adj_splits(p, B);
     // The minibatch table is an input, so all of its minibatches are sorted ahead in one launch
     // per batch of iterations; the iterations then run back to back on the sorted tables.
     const int per = (int)std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
@@ -2021,11 +2076,18 @@ static int solve_launches(spgm_plan *p, const int32_t *rows, int iters, int B, c
         const int32_t *rk = rows + (size_t)k0 * B;
         if ((rc = run_sort(p, rk, B, cnt, p->d_srt_all, st))) return rc;
         for (int k = 0; k < cnt; ++k) {
-            if ((rc = step_sorted(p, p->d_srt_all + (size_t)k * B, rk + (size_t)k * B, B, y, s, eta, alpha, st)))
-                return rc;
+            const int it = k0 + k;
+            const int4 *srt = p->d_srt_all + (size_t)k * B;
+            const SStep up = it == 0 ? SStep{} : SStep{p->d_gpart, buf[it & 1], nsplit, (int)p->N, step, alpha};
+            const float2 *s_prev = it == 0 ? s : buf[(it - 1) & 1];
+            if ((rc = run_forward_partials(p, srt, s_prev, B, st, up))) return rc;
+            if ((rc = run_row_reduce(p, srt, rk + (size_t)k * B, B, y, nullptr, p->d_rs, st))) return rc;
+            if ((rc = run_adjoint_partials(p, srt, B, st))) return rc;
         }
     }
-    return SPGM_OK;
+    k_col_reduce_to<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, nsplit, (int)p->N, buf[(iters - 1) & 1], s,
+                                                                step, alpha);
+    return launch_check("column reduce");
 }
 
 static int solve_prepare(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, const void *y, void *s,
@@ -2036,6 +2098,10 @@ static int solve_prepare(spgm_plan *p, const int32_t *rows, int32_t iters, int32
     if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve: iters must be >= 0");
     if ((rc = ensure_workspace(p, B))) return rc;
     if (iters == 0) return SPGM_OK;
+    if (!p->d_s_alt && hipMalloc(&p->d_s_alt, sizeof(float2) * (size_t)p->N) != hipSuccess) {
+        p->d_s_alt = nullptr;
+        return fail(SPGM_E_NOMEM, "spgm_solve: iterate buffer allocation failed");
+    }
     const size_t per = std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
     return ensure_sorted_batch(p, per * B);
 }
