@@ -135,6 +135,29 @@ def test_c0_structured_step_and_solve(bd):
     assert plan.status() == 0
 
 
+@pytest.mark.parametrize("iters", [1, 2, 5])
+def test_structured_solve_equals_repeated_steps(bd, iters):
+    """The structured solve reproduces `iters` single structured steps bit for bit (nonzero
+    start, active threshold)."""
+    cfg = W.CONFIGS["c0"]
+    geom = W.config_geometry("c0")
+    plan = bd.Plan(geom)
+    T, R, F = cfg["T"], cfg["R"], cfg["F"]
+    fs, ts, rs = W.draw_structured_subsets(T, R, F, 4, 8, 6, iters, seed=51)
+    y = cdev(W.random_complex(plan.M, seed=52))
+    s0 = W.random_complex(plan.N, seed=53).astype(np.complex64)
+    eta, alpha = 8e-3, 0.3 / iters
+    s_step = cdev(s0)
+    for k in range(iters):
+        plan.spgm_step_structured(idev(fs[k]), idev(ts[k]), idev(rs[k]), y, s_step, eta, alpha)
+    s_solve = cdev(s0)
+    plan.spgm_solve_structured(idev(fs), idev(ts), idev(rs), y, s_solve, eta, alpha)
+    ref = host(s_step)
+    assert np.count_nonzero(ref) not in (0, ref.size)
+    assert np.array_equal(host(s_solve), ref)
+    assert plan.status() == 0
+
+
 def test_c1_structured_full_size_sampled(bd):
     """c1 geometry with the structured minibatch (16 f, 16 Tx, 16 Rx; B = 4096 as the c1
     minibatch), full launch; the oracle evaluates 24 sampled rows and 64 sampled voxels."""
