@@ -106,7 +106,9 @@ int spgm_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d
               float eta, float alpha, void *stream);
 
 /* `iters` SPGM iterations; iteration k uses rows_d[k*B .. k*B + B - 1] (rows_d: int32[iters*B]).
- * Equivalent to `iters` calls of spgm_step.  iters >= 0. */
+ * Bitwise equal to `iters` calls of spgm_step.  iters >= 0.  Intermediate iterates alternate
+ * between s_d and a plan-owned buffer of N complex64 (allocated on the first solve); s_d holds
+ * the result when the call's work on `stream` is complete. */
 int spgm_solve(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, const void *y_d,
                void *s_d, float eta, float alpha, void *stream);
 
