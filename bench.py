@@ -60,12 +60,14 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel, workload):
-    """HBM bytes per launch from the committed counter runs, if the kernel source is unchanged."""
+def stored_traffic(kernel, workload, splits=None):
+    """HBM bytes per launch from the committed counter runs (per row split for the tile kernels),
+    if the kernel source is unchanged."""
     if not os.path.exists(TRAFFIC):
         return None
     data = json.load(open(TRAFFIC))
-    rec = data.get("%s/%s" % (kernel, workload))
+    key = "%s/%s" % (kernel, workload) + ("/splits%d" % splits if splits else "")
+    rec = data.get(key)
     if not rec or rec.get("source_sha") != source_sha():
         return None
     return rec.get("bytes_per_launch")
@@ -199,7 +201,8 @@ def main():
     kname, kavg = ("k_fwd_tile", fwd_avg) if fwd_avg >= adj_avg else ("k_adj_tile", adj_avg)
     achieved = entries * SLOTS_PER_ENTRY / kavg / 1e12
     peak = VALU_SLOTS_PER_S / 1e12
-    traffic = stored_traffic(kname, wl) if args.phase == "comp32" else None
+    kspl = None if splits is None else splits[0 if kname == "k_fwd_tile" else 1]
+    traffic = stored_traffic(kname, wl, kspl) if args.phase == "comp32" and kspl else None
     roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
