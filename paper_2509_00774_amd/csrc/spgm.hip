@@ -2386,13 +2386,16 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
             for (int which = 0; which < 2 && !rc; ++which) {
                 float best = 1e30f;
                 for (int rep = 0; rep < 4 && !rc; ++rep) {
-                    hipEventRecord(e0, st);
+                    if (hipEventRecord(e0, st) != hipSuccess) {
+                        rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune: event record failed");
+                        break;
+                    }
                     rc = which == 0 ? run_forward_partials(p, p->d_srt, ds, B, st) : run_adjoint_partials(p, p->d_srt, B, st);
-                    hipEventRecord(e1, st);
-                    hipEventSynchronize(e1);
                     float ms = 0.f;
-                    hipEventElapsedTime(&ms, e0, e1);
-                    if (rep > 0) best = std::min(best, ms);  // first launch warms up
+                    if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                        rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune: timing failed");
+                    if (!rc && rep > 0) best = std::min(best, ms);  // first launch warms up
                 }
                 if (which == 0 && best < best_f) {
                     best_f = best;
