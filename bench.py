@@ -457,7 +457,8 @@ def bench_batched(args, torch, binding, dev):
         "rel_l2_vs_oracle_after_1_iter": None if rel is None else float("%.3e" % rel),
         "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved / 1e12, 2),
                      "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK, 4),
-                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": round(kavg * 1e3, 5),
+                     "traffic": stored_traffic(kname, "c1k32"), "flops_per_launch": flops,
+                     "avg_launch_ms": round(kavg * 1e3, 5),
                      "fwd_mm_ms": round(fwd_avg * 1e3, 5), "adj_mm_ms": round(adj_avg * 1e3, 5),
                      "fwd_gentries_per_s": round(entries / fwd_avg / 1e9, 1),
                      "adj_gentries_per_s": round(entries / adj_avg / 1e9, 1),
@@ -556,7 +557,8 @@ def bench_structured(args, torch, binding, dev):
         "rel_l2_vs_oracle_after_iters": n_par,
         "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved / 1e12, 3),
                      "peak": 157.3, "unit": "TFLOP/s (float32 matrix cores)", "frac": round(achieved / 157.3e12, 4),
-                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": round(kavg * 1e3, 5),
+                     "traffic": stored_traffic(kname, "c1s"), "flops_per_launch": flops,
+                     "avg_launch_ms": round(kavg * 1e3, 5),
                      "sf_fwd_ms": round(fwd_avg * 1e3, 5), "sf_adj_ms": round(adj_avg * 1e3, 5),
                      "factors_per_launch": nf * (nt + nr) * N},
         "cpu_baseline": cpu,
@@ -662,7 +664,9 @@ def bench_tv(args, torch, binding, dev):
         "rel_l2_vs_oracle": None if rel is None else float("%.3e" % rel),
         "rel_l2_vs_oracle_after_iters": n_par,
         "roofline": {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
-                     "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4),
+                     "traffic": None if splits is None else stored_traffic(
+                         kname, "c1tv", splits[0 if kname == "k_fwd_tile" else 1]),
                      "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
                      "avg_launch_ms": round(kavg * 1e3, 5), "fwd_tile_ms": round(fwd_avg * 1e3, 5),
                      "adj_tile_ms": round(adj_avg * 1e3, 5)},
