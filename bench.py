@@ -41,7 +41,7 @@ STEP_SIZES = os.path.join(ROOT, "tests", "golden", "step_sizes.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 SOURCES = [os.path.join(ROOT, "paper_2509_00774_amd", "csrc", name)
            for name in ("spgm.hip", "spgm_mm.inc", "spgm_sf.inc", "spgm_reg.inc")] + [
-    os.path.join(ROOT, "include", "spgm.h")]
+    os.path.join(ROOT, "include", "spgm.h"), os.path.join(ROOT, "paper_2509_00774_amd", "build.py")]
 # Total-variation prox: algorithmic bytes per voxel and dual iteration (read b, r, w; write w, r
 # as three float32 components each).
 TV_BYTES_PER_VOXEL = 4 + 4 * 12
@@ -53,7 +53,8 @@ def log(*a):
 
 
 def source_sha():
-    """Fingerprint of every source of libspgm.so (counter records are void once any changes)."""
+    """Fingerprint of every source of libspgm.so and of its build flags (counter records are void
+    once any changes)."""
     h = hashlib.sha256()
     for path in SOURCES:
         h.update(open(path, "rb").read())

@@ -2,6 +2,11 @@
 
 Packed FP32 instructions are disabled (``-packed-fp32-ops``): the kernels are written with
 scalar float arithmetic and must not be turned into v_pk_* forms by the compiler.
+
+The machine scheduler runs its instruction-level-parallelism strategy (``max-ilp``): the tile
+kernels are bound by VALU issue, and ordering each row's independent sin/cos and FMA chains
+for latency rather than register pressure made the adjoint tile about 5 % faster on gfx950
+(forward unchanged) with no change of occupancy.
 """
 import os
 import subprocess
@@ -17,6 +22,7 @@ ARCH = os.environ.get("SPGM_OFFLOAD_ARCH", "gfx950")
 def hipcc_cmd(out):
     return ["hipcc", "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-sched-strategy=max-ilp",
             "-Wall", "-Wno-unused-result",
             "-I", os.path.join(ROOT, "include"), "-o", out, SRC]
 
