@@ -13,6 +13,7 @@ Functions and the passage each one follows:
 * :func:`prox_l1`                                        -- prox of alpha*||.||_1 used in Eq. 5
 * :meth:`Oracle.gradient`                                -- minibatch gradient (Sec. IV-A, Eq. 6)
 * :meth:`Oracle.step`, :meth:`Oracle.solve`              -- SPGM / PGM iteration (Sec. IV, Eq. 5)
+* :meth:`Oracle.solve_tol`                               -- the same until the termination rule of Sec. V
 * :meth:`Oracle.lambda_max`                              -- smallest lambda with zero minimiser of Eq. 3 with Eq. 4
 * :meth:`Oracle.lipschitz`                               -- power iteration on A_B^H A_B / B (step-size choice)
 * :func:`prox_elastic`, :func:`prox_tv_magnitude`,
@@ -68,6 +69,8 @@ def _lib():
             "ora_stochastic_gradient": (None, [g, _ip, C.c_int32, _dp, _dp, _dp]),
             "ora_step": (None, [g, _ip, C.c_int32, _dp, _dp, C.c_double, C.c_double]),
             "ora_solve": (None, [g, _ip, C.c_int32, C.c_int32, _dp, _dp, C.c_double, C.c_double]),
+            "ora_solve_tol": (C.c_int32, [g, _ip, C.c_int32, C.c_int32, _dp, _dp, C.c_double, C.c_double,
+                                          C.c_double]),
             "ora_grad3": (None, [C.c_int32, C.c_int32, C.c_int32, _dp, _dp]),
             "ora_grad3_adjoint": (None, [C.c_int32, C.c_int32, C.c_int32, _dp, _dp]),
             "ora_prox_elastic": (None, [_dp, C.c_int64, C.c_double, C.c_double]),
@@ -218,6 +221,17 @@ class Oracle:
         s = _c128(s0).reshape(-1).copy()
         _lib().ora_solve(C.byref(self._g), _ptr(rows, _ip), K, B, _ptr(y), _ptr(s), float(eta), float(alpha))
         return s
+
+    def solve_tol(self, rows_table, y, s0, eta: float, alpha: float, tol: float):
+        """Iterations of Eq. 5 until the termination rule of Sec. V (relative 2-norm change of the
+        magnitudes below ``tol``), at most K = len(rows_table).  Returns (s, iterations)."""
+        rows = _i32(rows_table)
+        K, B = rows.shape
+        y = _c128(y).reshape(-1)
+        s = _c128(s0).reshape(-1).copy()
+        done = _lib().ora_solve_tol(C.byref(self._g), _ptr(rows, _ip), K, B, _ptr(y), _ptr(s), float(eta),
+                                    float(alpha), float(tol))
+        return s, int(done)
 
     def lambda_max(self, y) -> float:
         """max_n |(A^H y)_n| / M: for lambda at or above it, s = 0 minimises Eq. 3 with Eq. 4."""
