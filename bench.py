@@ -12,7 +12,10 @@ GPU iterate against the FP64 oracle after the first iterations of the same solve
 roofline of the dominant kernel (timed live with HIP events on the library's stream), and
 the oracle's own rate on the host cores.
 
-Usage: python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--workload c1]
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--workload c2]
+       --workload c2     (default) the largest single-GPU configuration: 48 Tx + 48 Rx, 100
+                         frequencies, 128x128x64 voxels, B = 16384
+       --workload c1     mid-size: 32 Tx + 32 Rx, 64 frequencies, 64x64x32 voxels, B = 4096
        --workload c3     ragged batch of 96 scenes
        --workload c1k32  32 scenes of the c1 geometry through the shared-geometry batched path
        --workload c1s    c1 geometry with structured (16 f x 16 Tx x 16 Rx) minibatches
@@ -74,13 +77,192 @@ def stored_traffic(kernel, workload, splits=None):
     return rec.get("bytes_per_launch")
 
 
+def timed_solve(args, torch, plan, timed_rows, y, s, eta, alpha):
+    """Time len(timed_rows) SPGM iterations from s = 0 (graph replay unless --eager); returns the
+    wall time and the HIP-event totals of the two tile kernels."""
+    if not args.eager:
+        # The timed region replays the captured graph; the capture (and one replay) happens
+        # before it.  Kernel durations for the roofline come from an eager pass of the same
+        # launches right after, timed with HIP events on the library's stream.
+        plan.spgm_solve_graph(timed_rows, y, s, eta, alpha)
+        s.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.spgm_solve_graph(timed_rows, y, s, eta, alpha)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.zero_()
+        plan.spgm_plan_timing(True)
+        plan.spgm_plan_timing_read()
+        plan.spgm_solve(timed_rows, y, s, eta, alpha)
+        fwd_ms, fwd_n, adj_ms, adj_n = plan.spgm_plan_timing_read()
+        plan.spgm_plan_timing(False)
+    else:
+        plan.spgm_plan_timing(True)
+        plan.spgm_plan_timing_read()  # reset counters
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.spgm_solve(timed_rows, y, s, eta, alpha)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fwd_ms, fwd_n, adj_ms, adj_n = plan.spgm_plan_timing_read()
+        plan.spgm_plan_timing(False)
+    return t1 - t0, fwd_ms, fwd_n, adj_ms, adj_n
+
+
+def alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, splits, wl, phase):
+    """Roofline record of the slower tile kernel: VALU issue slots per launch (entries x the
+    9-slot minimum per entry) over its average HIP-event duration, against the issue ceiling."""
+    fwd_avg = fwd_ms / max(fwd_n, 1) * 1e-3
+    adj_avg = adj_ms / max(adj_n, 1) * 1e-3
+    kname, kavg = ("k_fwd_tile", fwd_avg) if fwd_avg >= adj_avg else ("k_adj_tile", adj_avg)
+    achieved = entries * SLOTS_PER_ENTRY / kavg / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
+    kspl = None if splits is None else splits[0 if kname == "k_fwd_tile" else 1]
+    traffic = stored_traffic(kname, wl, kspl) if phase == "comp32" and kspl else None
+    return {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+            "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
+            "avg_launch_ms": round(kavg * 1e3, 5),
+            "fwd_tile_ms": round(fwd_avg * 1e3, 5), "adj_tile_ms": round(adj_avg * 1e3, 5),
+            "fwd_gentries_per_s": round(entries / fwd_avg / 1e9, 1),
+            "adj_gentries_per_s": round(entries / adj_avg / 1e9, 1)}
+
+
+PHASE_DESC = {"comp32": "compensated fp32 (fp64 per-tile reference)", "f64": "fp64 distance and phase",
+              "naive32": "naive fp32"}
+
+
+def phase_mode_of(binding, name):
+    return {"comp32": binding.PHASE_COMP32, "f64": binding.PHASE_F64, "naive32": binding.PHASE_NAIVE32}[name]
+
+
+def bench_large(args, torch, binding, dev):
+    """The largest single-GPU configuration (48 Tx + 48 Rx, 100 frequencies, 128x128x64 voxels,
+    B = 16384): graph-replayed SPGM steps on the patches scene.  The oracle checks, at full size,
+    a forward of a dense random vector on a seeded 5 % of the minibatch rows and the first SPGM
+    step from s = 0 on a seeded 5 % of the voxels (that step needs only A_B^H y_B), and its time
+    on those samples is the CPU baseline."""
+    wl = "c2"
+    cfg = W.CONFIGS[wl]
+    geom = W.config_geometry(wl)
+    M, N = W.dims(geom)
+    B = cfg["B"]
+    K, Wm = args.steps, args.warmup
+    sj = json.load(open(STEP_SIZES))[wl]
+    eta = float(np.float32(sj["eta"]))
+    alpha = float(np.float32(sj["lambda"] * eta))
+    log("workload %s: T=%d R=%d F=%d M=%d N=%d B=%d; drawing %d minibatches" % (
+        wl, cfg["T"], cfg["R"], cfg["F"], M, N, B, 1 + Wm + K))
+    rows = W.config_rows(wl, K=1 + Wm + K)
+    s_true, idx = W.config_scene(wl)
+    plan = binding.Plan(geom, phase_mode=phase_mode_of(binding, args.phase))
+    splits = None if args.no_tune else plan.spgm_plan_autotune(B)
+    if splits:
+        log("autotuned row splits: forward %d, adjoint %d" % splits)
+    # Measurements: forward projection of the seeded scene in minibatch-sized row chunks, plus
+    # seeded noise at the workload's SNR.
+    s_true_d = torch.from_numpy(s_true.astype(np.complex64)).to(dev)
+    y0 = torch.empty(M, dtype=torch.complex64, device=dev)
+    for c0 in range(0, M, B):
+        c1 = min(M, c0 + B)
+        plan.spgm_forward(torch.arange(c0, c1, dtype=torch.int32, device=dev), s_true_d, out=y0[c0:c1])
+    y0_host = y0.cpu().numpy().astype(np.complex128)
+    y = torch.from_numpy(W.add_noise(y0_host, cfg["snr_db"], seed=cfg["seed"] + 2).astype(np.complex64)).to(dev)
+    rows_d = torch.from_numpy(rows).to(dev)
+    del s_true_d
+    # Parity samples, before the timed solve: a forward of a dense random vector on minibatch 0,
+    # and the first step from zero on minibatch 0.
+    rows0 = rows[0]
+    s_rand = W.random_complex(N, seed=cfg["seed"] + 20).astype(np.complex64)
+    y_rand = plan.spgm_forward(rows_d[0].contiguous(), torch.from_numpy(s_rand).to(dev)).cpu().numpy()
+    s1 = torch.zeros(N, dtype=torch.complex64, device=dev)
+    plan.spgm_solve(rows_d[:1].contiguous(), y, s1, eta, alpha)
+    s1_host = s1.cpu().numpy()
+    del s1
+    s = torch.zeros(N, dtype=torch.complex64, device=dev)
+    log("warmup %d steps" % Wm)
+    if Wm > 0:
+        plan.spgm_solve(rows_d[1:1 + Wm].contiguous(), y, s, eta, alpha)
+    s.zero_()
+    timed_rows = rows_d[1 + Wm:1 + Wm + K].contiguous()
+    dt, fwd_ms, fwd_n, adj_ms, adj_n = timed_solve(args, torch, plan, timed_rows, y, s, eta, alpha)
+    assert plan.spgm_plan_status() == 0
+    s_fin = s.cpu().numpy().astype(np.complex128)
+    nmse_truth_db = float(10.0 * np.log10(np.sum(np.abs(s_fin - s_true) ** 2) / np.sum(np.abs(s_true) ** 2)))
+    log("timed %d steps in %.4f s (%.4f ms/step); forward tile %.4f ms avg over %d, adjoint tile %.4f ms avg over %d" % (
+        K, dt, 1e3 * dt / K, fwd_ms / max(fwd_n, 1), fwd_n, adj_ms / max(adj_n, 1), adj_n))
+    entries = float(B) * N
+    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, splits, wl, args.phase)
+
+    cpu = None
+    par = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.Oracle(geom)
+        js = W.voxel_sample(B, 0.05, seed=cfg["seed"] + 21)
+        vs = W.voxel_sample(N, 0.05, seed=cfg["seed"] + 22)
+        ms = W.voxel_sample(M, 0.01, seed=cfg["seed"] + 23)
+        log("oracle: measurements (all %d rows of the %d-voxel scene)" % (M, idx.size))
+        y0_orc = orc.forward_sparse(np.arange(M), idx, s_true[idx])
+        y_orc = W.add_noise(y0_orc, cfg["snr_db"], seed=cfg["seed"] + 2)
+        par["rel_l2_scene_forward_1pct_rows"] = oracle.rel_l2(y0_host[ms], y0_orc[ms])
+        log("oracle: forward on %d rows x %d voxels, first step on %d voxels x %d rows, %d threads" % (
+            js.size, N, vs.size, B, oracle.num_threads()))
+        c0 = time.perf_counter()
+        y_ref = orc.forward(rows0[js], s_rand.astype(np.complex128))
+        c1 = time.perf_counter()
+        g_ref = orc.adjoint_voxels(rows0, y_orc[rows0], vs)
+        c2 = time.perf_counter()
+        s1_ref = oracle.prox_l1((eta / B) * g_ref, alpha)
+        par["rel_l2_forward_5pct_rows"] = oracle.rel_l2(y_rand[js], y_ref)
+        par["rel_l2_first_step_5pct_voxels"] = oracle.rel_l2(s1_host[vs], s1_ref)
+        par["first_step_nonzeros_in_sample"] = int(np.count_nonzero(s1_ref))
+        n_ent = float(js.size) * N + float(B) * vs.size
+        cpu = {"value": round(n_ent / (c2 - c0) / 1e9, 4), "unit": "Gentries/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "one step's entries on a seeded 5%% sample: forward of %d of the %d minibatch rows over all "
+                         "%d voxels (%.1f s) and the adjoint of the minibatch on %d voxels (%.1f s), FP64" % (
+                             js.size, B, N, c1 - c0, vs.size, c2 - c1)}
+        log("oracle parity: %s" % json.dumps(par))
+    out = {
+        "metric": "projector Gentries/s (A_B s + A_B^H r) and SPGM iters/s at fixed NMSE vs oracle",
+        "value": round(entries * K / dt / 1e9, 2),
+        "unit": "Gentries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(1e3 * dt / K, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2: %d Tx + %d Rx, %d frequencies, %dx%dx%d voxels, B=%d rows per minibatch, "
+                               "points plus three planar patches" % (cfg["T"], cfg["R"], cfg["F"], *cfg["grid"], B),
+                   "M": M, "N": N, "B": B, "hip_graph": not args.eager,
+                   "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]},
+                   "phase": PHASE_DESC[args.phase]},
+        "spgm_iters_per_s": round(K / dt, 2),
+        "rel_l2_vs_oracle": None if not par else float("%.3e" % max(
+            par["rel_l2_forward_5pct_rows"], par["rel_l2_first_step_5pct_voxels"])),
+        "parity_samples": {k: (float("%.3e" % v) if isinstance(v, float) else v) for k, v in par.items()},
+        "nmse_db_vs_truth_after_steps": round(nmse_truth_db, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c4", "c3", "c1k32", "c1s", "c1tv"],
-                    help="c3 is the ragged batch of 96 scenes advanced together")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c0", "c1", "c4", "c3", "c1k32", "c1s", "c1tv"],
+                    help="c2 (default) is the largest single-GPU configuration; c3 is the ragged batch of 96 "
+                         "scenes advanced together")
     ap.add_argument("--cpu-iters", type=int, default=5, help="iterations of the oracle timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the row-split autotuner")
@@ -113,6 +295,8 @@ def main():
         log("copy reference: %d bytes read, %d bytes written" % (a.numel() * 4, b.numel() * 4))
         del a, b
     wl = args.workload
+    if wl == "c2":
+        return bench_large(args, torch, binding, dev)
     if wl == "c3":
         return bench_ragged(args, torch, binding, dev)
     if wl == "c1k32":
@@ -135,8 +319,7 @@ def main():
     rows = W.config_rows(wl, K=max(Wm + K, args.cpu_iters))
     s_true, idx = W.config_scene(wl)
 
-    phase_mode = {"comp32": binding.PHASE_COMP32, "f64": binding.PHASE_F64, "naive32": binding.PHASE_NAIVE32}[args.phase]
-    plan = binding.Plan(geom, phase_mode=phase_mode)
+    plan = binding.Plan(geom, phase_mode=phase_mode_of(binding, args.phase))
     splits = None if args.no_tune else plan.spgm_plan_autotune(B)
     if splits:
         log("autotuned row splits: forward %d, adjoint %d" % splits)
@@ -160,35 +343,8 @@ def main():
     if Wm > 0:
         plan.spgm_solve(rows_d[:Wm].contiguous(), y, s, eta, alpha)
     timed_rows = rows_d[Wm:Wm + K].contiguous()
-    if not args.eager:
-        # The timed region replays the captured graph; the capture (and one replay) happens
-        # before it.  Kernel durations for the roofline come from an eager pass of the same
-        # launches right after, timed with HIP events on the library's stream.
-        plan.spgm_solve_graph(timed_rows, y, s, eta, alpha)
-        s.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.spgm_solve_graph(timed_rows, y, s, eta, alpha)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        s.zero_()
-        plan.spgm_plan_timing(True)
-        plan.spgm_plan_timing_read()
-        plan.spgm_solve(timed_rows, y, s, eta, alpha)
-        fwd_ms, fwd_n, adj_ms, adj_n = plan.spgm_plan_timing_read()
-        plan.spgm_plan_timing(False)
-    else:
-        plan.spgm_plan_timing(True)
-        plan.spgm_plan_timing_read()  # reset counters
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.spgm_solve(timed_rows, y, s, eta, alpha)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        fwd_ms, fwd_n, adj_ms, adj_n = plan.spgm_plan_timing_read()
-        plan.spgm_plan_timing(False)
+    dt, fwd_ms, fwd_n, adj_ms, adj_n = timed_solve(args, torch, plan, timed_rows, y, s, eta, alpha)
     assert plan.spgm_plan_status() == 0
-    dt = t1 - t0
     # reconstruction quality of the K-step solve from zero (both branches leave it in s)
     s_fin = s.cpu().numpy().astype(np.complex128)
     nmse_truth_db = float(10.0 * np.log10(np.sum(np.abs(s_fin - s_true) ** 2) / np.sum(np.abs(s_true) ** 2)))
@@ -197,20 +353,7 @@ def main():
 
     entries = float(B) * N
     value = entries * K / dt / 1e9
-    fwd_avg = fwd_ms / max(fwd_n, 1) * 1e-3
-    adj_avg = adj_ms / max(adj_n, 1) * 1e-3
-    kname, kavg = ("k_fwd_tile", fwd_avg) if fwd_avg >= adj_avg else ("k_adj_tile", adj_avg)
-    achieved = entries * SLOTS_PER_ENTRY / kavg / 1e12
-    peak = VALU_SLOTS_PER_S / 1e12
-    kspl = None if splits is None else splits[0 if kname == "k_fwd_tile" else 1]
-    traffic = stored_traffic(kname, wl, kspl) if args.phase == "comp32" and kspl else None
-    roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
-                "avg_launch_ms": round(kavg * 1e3, 5),
-                "fwd_tile_ms": round(fwd_avg * 1e3, 5), "adj_tile_ms": round(adj_avg * 1e3, 5),
-                "fwd_gentries_per_s": round(entries / fwd_avg / 1e9, 1),
-                "adj_gentries_per_s": round(entries / adj_avg / 1e9, 1)}
+    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, splits, wl, args.phase)
 
     cpu = None
     rel_vs_oracle = None
@@ -247,8 +390,8 @@ def main():
         "config": {"workload": "%s: %d Tx + %d Rx, %d frequencies, %dx%dx%d voxels, B=%d rows per minibatch" % (
             wl, cfg["T"], cfg["R"], cfg["F"], *cfg["grid"], B),
             "M": M, "N": N, "B": B, "hip_graph": not args.eager,
-            "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]}, "phase": {"comp32": "compensated fp32 (fp64 per-tile reference)",
-                                              "f64": "fp64 distance and phase", "naive32": "naive fp32"}[args.phase]},
+            "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]},
+            "phase": PHASE_DESC[args.phase]},
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if rel_vs_oracle is None else float("%.3e" % rel_vs_oracle),
         "rel_l2_vs_oracle_after_iters": n_par,

@@ -38,7 +38,7 @@ typedef enum spgm_status {
     SPGM_E_INVALID = 1,      /* bad argument: null pointer, size out of range, bad geometry */
     SPGM_E_NOMEM = 2,        /* device allocation failed */
     SPGM_E_DEVICE = 3,       /* HIP runtime error (no device, launch failure, ...) */
-    SPGM_E_NONFINITE = 4,    /* reserved: non-finite input detected */
+    SPGM_E_NONFINITE = 4,    /* a non-finite iterate was detected (spgm_solve_tol) */
     SPGM_E_UNSUPPORTED = 5,  /* valid request outside what the kernels support */
     SPGM_E_BADROW = 6        /* a row index outside [0, M) was seen on the device (sticky) */
 } spgm_status;
@@ -71,11 +71,26 @@ typedef struct spgm_geometry {
 
 typedef struct spgm_plan spgm_plan;
 
+/* Largest |argument| of sin/cos, in turns, that the compensated float32 phase (SPGM_PHASE_COMP32)
+ * can form for `geom` (Sec. II, Eq. 2, the phase f (d_T + d_R)/c): the per-tile reference phase
+ * is reduced to [-1/2, 1/2] in float64 and each voxel adds f/c (delta_T + delta_R), where each
+ * delta is the antenna's distance to the voxel minus its distance to the centre of the 8 x 8 x 4
+ * voxel brick, at most the brick's half-diagonal h; so *turns = 1/2 + 2 max_f (f/c) h.  The
+ * float32 argument carries a rounding error of half a unit in its last place, which grows with
+ * this bound; the kernels' accuracy was characterised for arguments within
+ * SPGM_COMP32_WINDOW_TURNS, and spgm_plan_create refuses COMP32 plans beyond it.  Host only: needs
+ * no device.  SPGM_E_INVALID for a NULL pointer, a count < 1, or a pitch, c or frequency that is
+ * not finite and > 0. */
+#define SPGM_COMP32_WINDOW_TURNS 8.0
+int spgm_phase_window(const spgm_geometry *geom, double *turns);
+
 /* Create a plan for `geom` on the current HIP device (Sec. II, Eq. 2 defines what it encodes).
  * Rejects (SPGM_E_INVALID): null pointers, any count < 1, M or N above 2^31 - 1, pitch or c or a
  * frequency <= 0, a non-finite value, or a voxel closer than 1e-9 m to an antenna (Eq. 2 is
- * singular there).  SPGM_E_UNSUPPORTED: min(T, R) > 64 or T + R > 512.  On success
- * *out owns device memory released by spgm_plan_destroy.  Synchronous. */
+ * singular there).  SPGM_E_UNSUPPORTED: min(T, R) > 64 or T + R > 512, or phase_mode
+ * SPGM_PHASE_COMP32 with spgm_phase_window above SPGM_COMP32_WINDOW_TURNS (a pitch too coarse for
+ * the highest frequency; SPGM_PHASE_F64 has no such limit).  On success *out owns device memory
+ * released by spgm_plan_destroy.  Synchronous. */
 int spgm_plan_create(spgm_plan **out, const spgm_geometry *geom, int32_t phase_mode);
 
 /* Release a plan and its device memory (NULL is a no-op).  Synchronises the plan's device. */
@@ -120,6 +135,26 @@ int spgm_solve(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B,
  * pays the capture and instantiation cost.  Same results as spgm_solve, bit for bit. */
 int spgm_solve_graph(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, const void *y_d,
                      void *s_d, float eta, float alpha, void *stream);
+
+/* spgm_solve until the termination rule of the experiments (Sec. V: the change in reflectivity
+ * magnitudes falls below a threshold), read as the relative 2-norm change
+ *     || |s^k| - |s^{k-1}| ||_2  <  tol || |s^{k-1}| ||_2,
+ * evaluated after every iteration k = 1, 2, ... (never met while s^{k-1} = 0).  The two sums are
+ * formed on the device in float64 in a fixed order.  Iterations are queued in groups of
+ * check_every (>= 1); after each group the host reads the group's records (one synchronisation
+ * per group) and, if the rule was met inside it, the iterate is brought back to the group's
+ * first iterate and advanced to the stopping iteration with the same kernels on the same rows,
+ * so s_d ends bitwise at the iterate the rule was met at (the same as spgm_solve with that many
+ * iterations).  tol <= 0 runs all `iters` iterations.  use_graph = 1 replays each full group as
+ * one captured HIP graph (kept while check_every, B, y_d, s_d, eta and alpha are unchanged).
+ * On return *iters_done is the number of iterations performed (the stopping k, or iters) and, if
+ * `changes` (host double[iters]) is not NULL, changes[k-1] holds the relative change of each
+ * performed iteration (+inf while s^{k-1} = 0).  Synchronous: returns after the stop is known.
+ * SPGM_E_NONFINITE: an iteration produced a non-finite change (a non-finite iterate); it stops
+ * there and *iters_done names it.  Other errors as spgm_solve. */
+int spgm_solve_tol(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_t B, const void *y_d,
+                   void *s_d, float eta, float alpha, double tol, int32_t check_every, int32_t use_graph,
+                   int32_t *iters_done, double *changes, void *stream);
 
 /* Backward of one unrolled SPGM iteration (differentiation of Eq. 5 with the gradient of
  * Eq. 6 with respect to its input iterate, step size and threshold):

@@ -40,9 +40,13 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_batch_create", "spgm_batch_destroy", "spgm_batch_plan", "spgm_batch_solve", "spgm_batch_status",
             "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched",
             "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured",
-            "spgm_prox", "spgm_step_reg", "spgm_solve_reg")
+            "spgm_prox", "spgm_step_reg", "spgm_solve_reg", "spgm_phase_window",
+            "spgm_solve_tol")
 
 _dp = C.POINTER(C.c_double)
+
+
+COMP32_WINDOW_TURNS = 8.0
 
 
 class SpgmGeometry(C.Structure):
@@ -110,6 +114,9 @@ def load_library(path: str = LIB_PATH):
         "spgm_prox": [vp, C.POINTER(SpgmRegularizer), vp, f32, vp],
         "spgm_step_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, vp, vp, f32, f32, vp],
         "spgm_solve_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, i32, vp, vp, f32, f32, vp],
+        "spgm_phase_window": [C.POINTER(SpgmGeometry), C.POINTER(C.c_double)],
+        "spgm_solve_tol": [vp, vp, i32, i32, vp, vp, f32, f32, C.c_double, i32, i32, C.POINTER(i32),
+                           C.POINTER(C.c_double), vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -149,6 +156,15 @@ def make_geometry_struct(geom):
     g.pitch = (C.c_double * 3)(*[float(v) for v in np.broadcast_to(geom["pitch"], (3,))])
     g.c = float(geom["c"])
     return g, [tx, rx, fr, pl]
+
+
+def phase_window(geom):
+    """Largest |sin/cos argument| in turns the compensated float32 phase can form for ``geom``."""
+    g, keep = make_geometry_struct(geom)
+    out = C.c_double()
+    _check(load_library().spgm_phase_window(C.byref(g), C.byref(out)))
+    del keep
+    return out.value
 
 
 def _stream_ptr(stream):
@@ -247,6 +263,27 @@ class Plan:
                                     _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
                                     float(eta), float(alpha), _stream_ptr(stream)))
         return s
+
+    def spgm_solve_tol(self, rows_table, y, s, eta, alpha, tol, check_every=50, use_graph=True, stream=None):
+        """Iterations of ``rows_table`` (iters, B) until the relative change of the magnitudes is
+        below ``tol``; returns (iterations performed, numpy array of their relative changes)."""
+        import torch
+        if rows_table.dim() != 2:
+            raise ValueError("rows_table must be 2-D (iters, B)")
+        K, B = rows_table.shape
+        done = C.c_int32()
+        changes = np.full(int(K), np.nan)
+        rc = self._lib.spgm_solve_tol(self._h, _dev(rows_table, torch.int32, "rows_table"), int(K), int(B),
+                                      _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
+                                      float(eta), float(alpha), float(tol), int(check_every), 1 if use_graph else 0,
+                                      C.byref(done), changes.ctypes.data_as(C.POINTER(C.c_double)),
+                                      _stream_ptr(stream))
+        if rc == SPGM_E_NONFINITE:
+            err = SpgmError(rc, self._lib.spgm_last_error().decode(errors="replace"))
+            err.iters_done = done.value
+            raise err
+        _check(rc)
+        return done.value, changes[:done.value]
 
     # --- other regularisers: kind REG_L1, REG_ELASTIC_NET (mu) or REG_TV_MAGNITUDE (tv_iters) ---
     def spgm_prox(self, v, alpha, kind, mu=0.0, tv_iters=0, stream=None):

@@ -990,6 +990,40 @@ __global__ __launch_bounds__(256) void k_col_reduce_to(const float2 *__restrict_
     col_reduce_body(gpart, nsplit, N, nullptr, s_in, s_out, step, alpha, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Column reduction of an iteration whose change of magnitudes is recorded (termination rule of
+// Sec. V): per voxel the gradient step and soft threshold in place, and per block the fixed-order
+// float64 sums of (|s_new| - |s_old|)^2 (part[block]) and |s_old|^2 (part[nb + block]).
+constexpr int kChgThreads = 256;
+__global__ __launch_bounds__(kChgThreads) void k_col_reduce_change(const float2 *__restrict__ gpart, int nsplit, int N,
+                                                                   float2 *__restrict__ s, float step, float alpha,
+                                                                   double *__restrict__ part) {
+    __shared__ double red[2][kChgThreads];
+    const int n = blockIdx.x * kChgThreads + threadIdx.x;
+    double d2 = 0.0, o2 = 0.0;
+    if (n < N) {
+        const float2 old = s[n];
+        const float2 nw = prox_step(old, split_sum(gpart, nsplit, N, n), step, alpha);
+        s[n] = nw;
+        o2 = (double)old.x * old.x + (double)old.y * old.y;
+        const double d = sqrt((double)nw.x * nw.x + (double)nw.y * nw.y) - sqrt(o2);
+        d2 = d * d;
+    }
+    red[0][threadIdx.x] = d2;
+    red[1][threadIdx.x] = o2;
+    __syncthreads();
+    for (int w = kChgThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = red[0][0];
+        part[gridDim.x + blockIdx.x] = red[1][0];
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Ragged batches: many scenes advanced by one launch per phase.  Each scene has a descriptor
 // in device memory; tile work is a list of (scene, brick, row range) items ordered longest
@@ -1242,6 +1276,22 @@ struct spgm_plan {
     // TV prox: magnitudes b [voxel] and the dual state w[2], r[2] [voxel] (ping-pong)
     float *d_tv_b = nullptr;
     float4 *d_tv_state = nullptr;
+    // solve to the termination rule: iterate at the start of a group of iterations, block
+    // partials and per-iteration (change^2, old^2) records, the group's rows for graph replay,
+    // and the captured group
+    float2 *d_tol_snap = nullptr;
+    double *d_tol_part = nullptr;
+    double *d_tol_rec = nullptr;
+    int32_t *d_tol_rows = nullptr;
+    size_t tol_group_cap = 0, tol_rows_cap = 0;
+    hipGraph_t tol_graph = nullptr;
+    hipGraphExec_t tol_exec = nullptr;
+    struct {
+        int group, B;
+        const void *y;
+        void *s;
+        float eta, alpha;
+    } tol_key{};
 };
 
 // A batch of independent scenes (one plan each) advanced together.
@@ -1293,6 +1343,10 @@ void drop_graph(spgm_plan *p) {
     if (p->graph) hipGraphDestroy(p->graph);
     p->graph_exec = nullptr;
     p->graph = nullptr;
+    if (p->tol_exec) hipGraphExecDestroy(p->tol_exec);
+    if (p->tol_graph) hipGraphDestroy(p->tol_graph);
+    p->tol_exec = nullptr;
+    p->tol_graph = nullptr;
 }
 
 int ensure_workspace(spgm_plan *p, int B) {
@@ -1824,14 +1878,50 @@ static void build_ltab(spgm_plan *p) {
     g.ltab_mode = p->phase_mode;
 }
 
+// Counts, pointers, speed, pitch, centre, frequencies and pulse of a geometry (host only).
+static int check_geometry_basic(const spgm_geometry *gm, const char *who) {
+    if (!gm) return fail(SPGM_E_INVALID, "%s: geometry is NULL", who);
+    if (gm->n_tx < 1 || gm->n_rx < 1 || gm->n_freq < 1 || gm->nx < 1 || gm->ny < 1 || gm->nz < 1)
+        return fail(SPGM_E_INVALID, "%s: every count must be >= 1", who);
+    if (!gm->tx_xyz || !gm->rx_xyz || !gm->freq_hz)
+        return fail(SPGM_E_INVALID, "%s: tx_xyz, rx_xyz and freq_hz must be non-NULL", who);
+    if (!(std::isfinite(gm->c) && gm->c > 0)) return fail(SPGM_E_INVALID, "%s: c must be finite and > 0", who);
+    if (!finite3(gm->centre) || !finite3(gm->pitch) || !(gm->pitch[0] > 0 && gm->pitch[1] > 0 && gm->pitch[2] > 0))
+        return fail(SPGM_E_INVALID, "%s: centre must be finite and pitch > 0", who);
+    for (int64_t f = 0; f < gm->n_freq; ++f) {
+        if (!(std::isfinite(gm->freq_hz[f]) && gm->freq_hz[f] > 0))
+            return fail(SPGM_E_INVALID, "%s: frequency %lld is not finite and > 0", who, (long long)f);
+        if (gm->pulse && !(std::isfinite(gm->pulse[2 * f]) && std::isfinite(gm->pulse[2 * f + 1])))
+            return fail(SPGM_E_INVALID, "%s: pulse %lld is not finite", who, (long long)f);
+    }
+    return SPGM_OK;
+}
+
+// Bound on the float32 argument of sin/cos in the compensated scheme, in turns: the reference
+// phase reduced to [-1/2, 1/2] plus f/c times the two antennas' distance offsets, each at most the
+// half-diagonal h of the voxel brick (triangle inequality).
+static double phase_window_turns(const spgm_geometry *gm) {
+    const double hx = 0.5 * (kBX - 1) * gm->pitch[0], hy = 0.5 * (kBY - 1) * gm->pitch[1];
+    const double hz = 0.5 * (kBZ - 1) * gm->pitch[2];
+    const double h = std::sqrt(hx * hx + hy * hy + hz * hz);
+    double fmax = 0.0;
+    for (int64_t f = 0; f < gm->n_freq; ++f) fmax = std::max(fmax, gm->freq_hz[f]);
+    return 0.5 + 2.0 * (fmax / gm->c) * h;
+}
+
+int spgm_phase_window(const spgm_geometry *gm, double *turns) {
+    int rc;
+    if (!turns) return fail(SPGM_E_INVALID, "spgm_phase_window: turns is NULL");
+    if ((rc = check_geometry_basic(gm, "spgm_phase_window"))) return rc;
+    *turns = phase_window_turns(gm);
+    return ok();
+}
+
 int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mode) {
+    int rc;
     if (!out) return fail(SPGM_E_INVALID, "spgm_plan_create: out is NULL");
     *out = nullptr;
-    if (!gm) return fail(SPGM_E_INVALID, "spgm_plan_create: geometry is NULL");
-    if (gm->n_tx < 1 || gm->n_rx < 1 || gm->n_freq < 1 || gm->nx < 1 || gm->ny < 1 || gm->nz < 1)
-        return fail(SPGM_E_INVALID, "spgm_plan_create: every count must be >= 1");
-    if (!gm->tx_xyz || !gm->rx_xyz || !gm->freq_hz)
-        return fail(SPGM_E_INVALID, "spgm_plan_create: tx_xyz, rx_xyz and freq_hz must be non-NULL");
+    if ((rc = check_geometry_basic(gm, "spgm_plan_create"))) return rc;
     if (phase_mode != SPGM_PHASE_COMP32 && phase_mode != SPGM_PHASE_F64 && phase_mode != SPGM_PHASE_NAIVE32)
         return fail(SPGM_E_INVALID, "spgm_plan_create: unknown phase mode %d", phase_mode);
     const int64_t T = gm->n_tx, R = gm->n_rx, F = gm->n_freq;
@@ -1840,15 +1930,11 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     if (M > INT32_MAX || N > INT32_MAX) return fail(SPGM_E_INVALID, "spgm_plan_create: M or N exceeds 2^31-1");
     if (std::min(T, R) > kMaxL || T + R > kMaxAnt)
         return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: needs min(T,R) <= %d and T+R <= %d", kMaxL, kMaxAnt);
-    if (!(std::isfinite(gm->c) && gm->c > 0)) return fail(SPGM_E_INVALID, "spgm_plan_create: c must be finite and > 0");
-    if (!finite3(gm->centre) || !finite3(gm->pitch) || !(gm->pitch[0] > 0 && gm->pitch[1] > 0 && gm->pitch[2] > 0))
-        return fail(SPGM_E_INVALID, "spgm_plan_create: centre must be finite and pitch > 0");
-    for (int64_t f = 0; f < F; ++f) {
-        if (!(std::isfinite(gm->freq_hz[f]) && gm->freq_hz[f] > 0))
-            return fail(SPGM_E_INVALID, "spgm_plan_create: frequency %lld is not finite and > 0", (long long)f);
-        if (gm->pulse && !(std::isfinite(gm->pulse[2 * f]) && std::isfinite(gm->pulse[2 * f + 1])))
-            return fail(SPGM_E_INVALID, "spgm_plan_create: pulse %lld is not finite", (long long)f);
-    }
+    if (phase_mode == SPGM_PHASE_COMP32 && phase_window_turns(gm) > SPGM_COMP32_WINDOW_TURNS)
+        return fail(SPGM_E_UNSUPPORTED,
+                    "spgm_plan_create: the compensated float32 phase can reach %.2f turns for this pitch and "
+                    "frequency, beyond the %.0f-turn window its accuracy holds in; use SPGM_PHASE_F64",
+                    phase_window_turns(gm), (double)SPGM_COMP32_WINDOW_TURNS);
     // Antenna positions; voxels must stay away from every antenna (Eq. 2 divides by distances).
     const double lo[3] = {gm->centre[0] - 0.5 * (gm->nx - 1) * gm->pitch[0],
                           gm->centre[1] - 0.5 * (gm->ny - 1) * gm->pitch[1],
@@ -1992,6 +2078,10 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_mm_r);
     hipFree(p->d_mm_gpart);
     hipFree(p->d_sf_rows);
+    hipFree(p->d_tol_snap);
+    hipFree(p->d_tol_part);
+    hipFree(p->d_tol_rec);
+    hipFree(p->d_tol_rows);
     drop_graph(p);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);
     for (hipEvent_t e : p->ev_fwd) hipEventDestroy(e);
@@ -2223,6 +2313,194 @@ int spgm_solve_graph(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B
     }
     const hipError_t e = hipGraphLaunch(p->graph_exec, (hipStream_t)stream);
     if (e != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_solve_graph: launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+// ---------------------------------------------------------------- solve to the termination rule
+// One group of `cnt` iterations on rows[0 .. cnt*B): sort, then per iteration the forward, the
+// residual, the adjoint and the column reduction that also forms the iteration's change record
+// rec[2j] = sum (|s^k| - |s^{k-1}|)^2, rec[2j+1] = sum |s^{k-1}|^2 (fixed-order float64 sums).
+static int tol_group_launches(spgm_plan *p, const int32_t *rows, int cnt, int B, const float2 *y, float2 *s,
+                              float eta, float alpha, double *rec, hipStream_t st) {
+    int rc;
+    if ((rc = run_sort(p, rows, B, cnt, p->d_srt_all, st))) return rc;
+    const int nb = (int)((p->N + kChgThreads - 1) / kChgThreads);
+    for (int j = 0; j < cnt; ++j) {
+        const int4 *srt = p->d_srt_all + (size_t)j * B;
+        if ((rc = run_forward_partials(p, srt, s, B, st))) return rc;
+        if ((rc = run_row_reduce(p, srt, rows + (size_t)j * B, B, y, nullptr, p->d_rs, st))) return rc;
+        if ((rc = run_adjoint_partials(p, srt, B, st))) return rc;
+        k_col_reduce_change<<<nb, kChgThreads, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, s, eta / (float)B,
+                                                        alpha, p->d_tol_part);
+        if ((rc = launch_check("column reduce (change)"))) return rc;
+        k_sum_partials<<<1, 256, 0, st>>>(p->d_tol_part, nb, rec + 2 * j, rec + 2 * j + 1);
+        if ((rc = launch_check("change sum"))) return rc;
+    }
+    return SPGM_OK;
+}
+
+static int tol_prepare(spgm_plan *p, int group, int B) {
+    int rc;
+    const size_t nb = (size_t)((p->N + kChgThreads - 1) / kChgThreads);
+    if (!p->d_tol_snap) {
+        if (hipMalloc(&p->d_tol_snap, sizeof(float2) * (size_t)p->N) != hipSuccess ||
+            hipMalloc(&p->d_tol_part, sizeof(double) * 2 * nb) != hipSuccess) {
+            hipFree(p->d_tol_snap);
+            p->d_tol_snap = nullptr;
+            p->d_tol_part = nullptr;
+            return fail(SPGM_E_NOMEM, "spgm_solve_tol: workspace allocation failed");
+        }
+    }
+    if ((size_t)group > p->tol_group_cap) {
+        drop_graph(p);
+        hipFree(p->d_tol_rec);
+        p->d_tol_rec = nullptr;
+        p->tol_group_cap = 0;
+        if (hipMalloc(&p->d_tol_rec, sizeof(double) * 2 * ((size_t)group + 1)) != hipSuccess)
+            return fail(SPGM_E_NOMEM, "spgm_solve_tol: record allocation failed");
+        p->tol_group_cap = (size_t)group;
+    }
+    if ((size_t)group * B > p->tol_rows_cap) {
+        drop_graph(p);
+        hipFree(p->d_tol_rows);
+        p->d_tol_rows = nullptr;
+        p->tol_rows_cap = 0;
+        if (hipMalloc(&p->d_tol_rows, sizeof(int32_t) * (size_t)group * B) != hipSuccess)
+            return fail(SPGM_E_NOMEM, "spgm_solve_tol: row buffer allocation failed");
+        p->tol_rows_cap = (size_t)group * B;
+    }
+    if ((rc = ensure_sorted_batch(p, (size_t)group * B))) return rc;
+    return SPGM_OK;
+}
+
+// Graph of one full group on the plan's row buffer (captured once per group size, B, y, s, eta,
+// alpha; replayed after the group's rows are copied into the buffer).
+static int tol_group_graph(spgm_plan *p, int group, int B, const float2 *y, float2 *s, float eta, float alpha,
+                           hipStream_t st) {
+    const bool same = p->tol_exec && p->tol_key.group == group && p->tol_key.B == B && p->tol_key.y == y &&
+                      p->tol_key.s == s && p->tol_key.eta == eta && p->tol_key.alpha == alpha;
+    if (!same) {
+        if (p->tol_exec) hipGraphExecDestroy(p->tol_exec);
+        if (p->tol_graph) hipGraphDestroy(p->tol_graph);
+        p->tol_exec = nullptr;
+        p->tol_graph = nullptr;
+        if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(SPGM_E_DEVICE, "spgm_solve_tol: stream creation failed");
+        const bool timing = p->timing;
+        p->timing = false;
+        if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            p->timing = timing;
+            return fail(SPGM_E_DEVICE, "spgm_solve_tol: capture failed to start");
+        }
+        int rc = tol_group_launches(p, p->d_tol_rows, group, B, y, s, eta, alpha, p->d_tol_rec, p->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        p->timing = timing;
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess || !g) return fail(SPGM_E_DEVICE, "spgm_solve_tol: capture failed: %s", hipGetErrorString(e));
+        if (hipGraphInstantiate(&p->tol_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return fail(SPGM_E_DEVICE, "spgm_solve_tol: graph instantiation failed");
+        }
+        p->tol_graph = g;
+        p->tol_key.group = group;
+        p->tol_key.B = B;
+        p->tol_key.y = y;
+        p->tol_key.s = s;
+        p->tol_key.eta = eta;
+        p->tol_key.alpha = alpha;
+    }
+    const hipError_t e = hipGraphLaunch(p->tol_exec, st);
+    if (e != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_solve_tol: graph launch failed: %s", hipGetErrorString(e));
+    return SPGM_OK;
+}
+
+int spgm_solve_tol(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, const void *y, void *s, float eta,
+                   float alpha, double tol, int32_t check_every, int32_t use_graph, int32_t *iters_done,
+                   double *changes, void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    if (!iters_done) return fail(SPGM_E_INVALID, "spgm_solve_tol: iters_done is NULL");
+    if (iters < 0) return fail(SPGM_E_INVALID, "spgm_solve_tol: iters must be >= 0");
+    if (check_every < 1) return fail(SPGM_E_INVALID, "spgm_solve_tol: check_every must be >= 1");
+    if (std::isnan(tol)) return fail(SPGM_E_INVALID, "spgm_solve_tol: tol is NaN");
+    *iters_done = 0;
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B))) return rc;
+    if (iters == 0) return ok();
+    const int group = std::max(1, std::min<int>(std::min(check_every, iters), (int)(kSolveSortRows / (size_t)B)));
+    if ((rc = tol_prepare(p, group, B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    float2 *sv = (float2 *)s;
+    const float2 *yv = (const float2 *)y;
+    const size_t sbytes = sizeof(float2) * (size_t)p->N;
+    std::vector<double> rec(2 * (size_t)group);
+    const double tol2 = tol > 0 ? tol * tol : -1.0;
+    for (int k = 0; k < iters;) {
+        const int cnt = std::min(group, iters - k);
+        const int32_t *rk = rows + (size_t)k * B;
+        if (hipMemcpyAsync(p->d_tol_snap, sv, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return fail(SPGM_E_DEVICE, "spgm_solve_tol: iterate copy failed");
+        const int32_t *rows_used = rk;
+        if (use_graph && cnt == group) {
+            if (hipMemcpyAsync(p->d_tol_rows, rk, sizeof(int32_t) * (size_t)cnt * B, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+                return fail(SPGM_E_DEVICE, "spgm_solve_tol: row copy failed");
+            if ((rc = tol_group_graph(p, group, B, yv, sv, eta, alpha, st))) return rc;
+            rows_used = p->d_tol_rows;
+        } else if ((rc = tol_group_launches(p, rk, cnt, B, yv, sv, eta, alpha, p->d_tol_rec, st))) {
+            return rc;
+        }
+        if (hipMemcpyAsync(rec.data(), p->d_tol_rec, sizeof(double) * 2 * cnt, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(SPGM_E_DEVICE, "spgm_solve_tol: record read failed");
+        int stop = -1;
+        bool bad = false;
+        for (int j = 0; j < cnt; ++j) {
+            const double d2 = rec[2 * j], o2 = rec[2 * j + 1];
+            if (changes) changes[k + j] = o2 > 0 ? std::sqrt(d2 / o2) : HUGE_VAL;
+            if (!std::isfinite(d2) || !std::isfinite(o2)) {
+                stop = j;
+                bad = true;
+                break;
+            }
+            if (d2 < tol2 * o2) {
+                stop = j;
+                break;
+            }
+        }
+        if (stop < 0) {
+            k += cnt;
+            continue;
+        }
+        if (stop < cnt - 1) {
+            // Back to the group's first iterate and forward to the stopping one: the same kernels
+            // on the same sorted rows, so the iterate is bitwise the one the rule was met at.
+            if (hipMemcpyAsync(sv, p->d_tol_snap, sbytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return fail(SPGM_E_DEVICE, "spgm_solve_tol: iterate restore failed");
+            const int nb = (int)((p->N + kChgThreads - 1) / kChgThreads);
+            for (int j = 0; j <= stop; ++j) {
+                const int4 *srt = p->d_srt_all + (size_t)j * B;
+                if ((rc = run_forward_partials(p, srt, sv, B, st))) return rc;
+                if ((rc = run_row_reduce(p, srt, rows_used + (size_t)j * B, B, yv, nullptr, p->d_rs, st))) return rc;
+                if ((rc = run_adjoint_partials(p, srt, B, st))) return rc;
+                k_col_reduce_change<<<nb, kChgThreads, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, sv,
+                                                                eta / (float)B, alpha, p->d_tol_part);
+                if ((rc = launch_check("column reduce (change)"))) return rc;
+            }
+            if (hipStreamSynchronize(st) != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_solve_tol: replay failed");
+        }
+        *iters_done = k + stop + 1;
+        if (bad)
+            return fail(SPGM_E_NONFINITE, "spgm_solve_tol: the iterate of iteration %d is not finite", k + stop + 1);
+        return ok();
+    }
+    *iters_done = iters;
     return ok();
 }
 

@@ -16,8 +16,9 @@ minibatches of the composition for SPGM ("own step").  The paper uses one step s
 run; that protocol is run as well ("PGM step": SPGM at the PGM step size), and it is reported
 as diverged when the iterate grows without bound.  The synthetic scene has 0.2 % non-zero
 voxels (156 points; with 1 584 measurements a 2 % scene is beyond what l1 recovers).
-Runtime = iterations to termination x the measured time of one iteration (library launches
-only, timed over a block of iterations).  Beside the protocol's termination rule, every run
+Runtime = measured wall-clock time of the library's solve to termination (spgm_solve_tol: the
+termination rule evaluated on the device after every iteration, read back once per group of 50
+iterations).  Beside the protocol's termination rule, every run
 records the PSNR against a converged PGM reconstruction (5 000 full iterations) every 10
 iterations, and the table gives the runtime until it first reaches 30 and 40 dB ("PGM to
 convergence" is PGM's own approach to that reference).  Every iteration runs on the pair
@@ -106,57 +107,48 @@ class Problem:
         return [self.torch.from_numpy(x).to(self.dev) for x in (fs, ts, rs)]
 
     def run(self, comp, eta, alpha, tol, max_iters, seed, record_every=10, ref=None):
-        """SPGM (or PGM for the full composition) from zero until the change in magnitudes is
-        below tol.  Returns (s, iterations, terminated, curve); curve rows are [iteration, change,
-        PSNR against `ref` (a device tensor) or None] every `record_every` iterations."""
-        torch = self.torch
-        chunk = 50
-        s = torch.zeros(self.N, dtype=torch.complex64, device=self.dev)
-        prev = torch.empty_like(s)
-        changes = torch.empty(chunk, dtype=torch.float32, device=self.dev)
-        psnrs = torch.full((chunk,), float("nan"), dtype=torch.float32, device=self.dev)
-        if ref is not None:
-            ref_n = torch.abs(ref) / torch.clamp(torch.max(torch.abs(ref)), min=1e-30)
-        curve = []
-        k = 0
-        while k < max_iters:
-            n = min(chunk, max_iters - k)
-            rows = self.row_table(comp, n, seed + k)
-            for j in range(n):
-                prev.copy_(s)
-                self.plan.spgm_step(rows[j], self.y, s, eta, alpha)
-                den = torch.linalg.vector_norm(torch.abs(prev))
-                num = torch.linalg.vector_norm(torch.abs(s) - torch.abs(prev))
-                changes[j] = torch.where(den > 0, num / torch.clamp(den, min=1e-30), torch.full_like(den, float("inf")))
-                if ref is not None and (k + j + 1) % record_every == 0:
-                    a = torch.abs(s) / torch.clamp(torch.max(torch.abs(s)), min=1e-30)
-                    psnrs[j] = -10.0 * torch.log10(torch.mean((a - ref_n) ** 2))
-            ch = changes[:n].cpu().numpy()
-            ps = psnrs[:n].cpu().numpy()
-            for j in range(n):
-                if (k + j + 1) % record_every == 0:
-                    curve.append([k + j + 1, float(ch[j]), None if ref is None else float(ps[j])])
-            if np.any(np.isnan(ch)) or not (float(torch.linalg.vector_norm(s).item()) < 1e6):
-                return s, k + n, "diverged", curve
-            hit = np.nonzero(ch < tol)[0]
-            if hit.size:
-                # the iterate is kept at the end of this chunk; the count is the first crossing
-                return s, k + int(hit[0]) + 1, True, curve
-            k += n
-        return s, max_iters, False, curve
+        """SPGM (or PGM for the full composition) from zero until the library's termination rule
+        holds (spgm_solve_tol, at most max_iters iterations).
 
-    def time_per_iteration(self, comp, eta, alpha, iters, seed):
-        """Seconds per SPGM iteration of the library alone (one solve call over `iters`)."""
+        Returns (s, iterations, status, curve, wall_s): status is True when the rule was met,
+        False at max_iters, "diverged" for a non-finite iterate; wall_s is the measured
+        wall-clock time of one uninterrupted solve to termination (graph-replayed groups of 50
+        iterations, one host read of the change records per group).  curve rows are
+        [iteration, change, PSNR against `ref` or None] every `record_every` iterations, from a
+        second pass in segments of `record_every` iterations that reproduces the same iterates
+        (the kernels and the rule do not depend on how iterations are grouped; checked)."""
         torch = self.torch
-        rows = self.row_table(comp, iters, seed)
+        rows = self.row_table(comp, max_iters, seed)
         s = torch.zeros(self.N, dtype=torch.complex64, device=self.dev)
-        self.plan.spgm_solve(rows[:5].contiguous(), self.y, s, eta, alpha)
-        s.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        self.plan.spgm_solve(rows, self.y, s, eta, alpha)
+        try:
+            k, changes = self.plan.spgm_solve_tol(rows, self.y, s, eta, alpha, tol, check_every=50, use_graph=True)
+            status = bool(k < max_iters or (tol > 0 and k > 0 and changes[-1] < tol))
+        except self.bd.SpgmError as e:
+            if e.code != self.bd.SPGM_E_NONFINITE:
+                raise
+            k, status = e.iters_done, "diverged"
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / iters
+        wall = time.perf_counter() - t0
+        curve = []
+        s2 = torch.zeros_like(s)
+        ref_h = None if ref is None else ref.cpu().numpy()
+        for k0 in range(0, k, record_every):
+            n = min(record_every, k - k0)
+            try:
+                _, ch = self.plan.spgm_solve_tol(rows[k0:k0 + n], self.y, s2, eta, alpha, 0.0, check_every=n,
+                                                 use_graph=True)
+            except self.bd.SpgmError as e:
+                if e.code != self.bd.SPGM_E_NONFINITE:
+                    raise
+                break
+            if (k0 + n) % record_every == 0:
+                p = None if ref_h is None else psnr_normalised(s2.cpu().numpy(), ref_h)
+                curve.append([k0 + n, float(ch[-1]), p])
+        if status != "diverged":
+            assert torch.equal(s, s2), "segmented pass must reproduce the solve"
+        return s, k, status, curve, wall
 
 
 def main():
@@ -164,7 +156,6 @@ def main():
     ap.add_argument("--out", default="profiles/study_P")
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--max-iters", type=int, default=20000)
-    ap.add_argument("--time-iters", type=int, default=400)
     args = ap.parse_args()
     import torch
 
@@ -179,7 +170,7 @@ def main():
     print("[study] lambda %.4e; PGM step 1/L_full = %.4e" % (lam, eta_pgm), flush=True)
 
     # A converged PGM reference beside the protocol's (which stops at the 1e-3 change rule).
-    s_conv, _, _, _ = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), 0.0, 5000, 1)
+    s_conv, _, _, _, _ = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), 0.0, 5000, 1, record_every=5000)
     s_conv_h = s_conv.cpu().numpy().astype(np.complex128)
     thresholds = (30.0, 40.0)
 
@@ -204,13 +195,13 @@ def main():
         return rec
 
     records = {}
-    t_pgm = P.time_per_iteration(full, eta_pgm, lam * eta_pgm, args.time_iters // 4, 1)
     # PGM's own approach to the converged reconstruction (no termination rule), for the
     # time-to-quality columns
-    _, k_c, _, curve_c = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), 0.0, 5000, 1, ref=s_conv)
-    records["PGM to convergence"] = entry("PGM", full, eta_pgm, k_c, False, t_pgm, s_conv_h, curve_c, None)
-    s_pgm, k_pgm, term_pgm, curve_pgm = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), args.tol,
-                                              args.max_iters, 1, ref=s_conv)
+    _, k_c, _, curve_c, wall_c = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), 0.0, 5000, 1, ref=s_conv)
+    records["PGM to convergence"] = entry("PGM", full, eta_pgm, k_c, False, wall_c / k_c, s_conv_h, curve_c, None)
+    s_pgm, k_pgm, term_pgm, curve_pgm, wall_pgm = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), args.tol,
+                                                        args.max_iters, 1, ref=s_conv)
+    t_pgm = wall_pgm / max(k_pgm, 1)
     s_pgm_h = s_pgm.cpu().numpy().astype(np.complex128)
     records["PGM"] = entry("PGM", full, eta_pgm, k_pgm, term_pgm, t_pgm, s_pgm_h, curve_pgm, None)
     print("[study] PGM: %d iterations (terminated %s), %.1f us/iteration, runtime %.4f s, NMSE %.2f dB" % (
@@ -221,8 +212,8 @@ def main():
         L_b = max(P.top_eigenvalue(fs[j], ts[j], rs[j], seed=ci * 4 + j) for j in range(4))
         for tag, eta in (("own step", float(np.float32(1.0 / L_b))), ("PGM step", eta_pgm)):
             alpha = float(np.float32(lam * eta))
-            t_it = P.time_per_iteration(comp, eta, alpha, args.time_iters, 500 + ci)
-            s, k, term, curve = P.run(comp, eta, alpha, args.tol, args.max_iters, 100000 * (ci + 1), ref=s_conv)
+            s, k, term, curve, wall = P.run(comp, eta, alpha, args.tol, args.max_iters, 100000 * (ci + 1), ref=s_conv)
+            t_it = wall / max(k, 1)
             sh = s.cpu().numpy().astype(np.complex128)
             rec = entry("SPGM", comp, eta, k, term, t_it, sh, curve, s_pgm_h)
             rec["speedup_vs_pgm"] = pgm_runtime / max(k * t_it, 1e-30)
@@ -235,7 +226,7 @@ def main():
     # PGM* : PGM under the time budget of SPGM (4, 4, 3) (own step)
     budget = records["SPGM 4,4,3 own step"]["runtime_s"]
     k_star = max(1, int(budget / t_pgm))
-    s_star, _, _, _ = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), 0.0, k_star, 1)
+    s_star, _, _, _, _ = P.run(full, eta_pgm, float(np.float32(lam * eta_pgm)), 0.0, k_star, 1, record_every=k_star)
     sh = s_star.cpu().numpy().astype(np.complex128)
     records["PGM*"] = entry("PGM*", full, eta_pgm, k_star, False, t_pgm, sh, [], s_pgm_h)
     print("[study] PGM* (budget of SPGM (4,4,3), %.4f s): %d iterations, PSNR vs PGM %.2f dB, NMSE %.2f dB" % (

@@ -180,6 +180,13 @@ def draw_structured_rows(T, R, F, nf, nt, nr, K, seed=0):
     return np.stack([structured_rows(T, R, fs[k], ts[k], rs[k]) for k in range(K)])
 
 
+def voxel_sample(n, fraction, seed=0):
+    """Sorted seeded sample of round(fraction * n) distinct indices in [0, n) (row or voxel
+    subsamples on which the full-size results are checked)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=max(1, int(round(fraction * n))), replace=False))
+
+
 def random_complex(n, seed=0, dtype=np.complex128):
     """Dense standard circular complex Gaussian vector (for projector parity inputs)."""
     rng = np.random.default_rng(seed)

@@ -99,3 +99,44 @@ def test_product_path_refuses_to_run_without_library(tmp_path, monkeypatch):
 
 def test_autotune_rejects_null_plan(lib):
     assert lib.spgm_plan_autotune(None, 16, None, None, None) == bd.SPGM_E_INVALID
+
+
+def test_phase_window_bound(lib):
+    """1/2 + 2 (f_max/c) h, h the half-diagonal of the 8 x 8 x 4 brick: 0.5 + 2 (30 GHz / c) *
+    sqrt(2 (17.5 mm)^2 + (7.5 mm)^2) = 5.675 turns for the 5 mm, 20-30 GHz geometry."""
+    geom = W.make_geometry(8, 8, 16, (20e9, 30e9), (16, 16, 8), 5e-3, 0.25, 0.2, seed=1)
+    h = np.sqrt(2 * 17.5e-3 ** 2 + 7.5e-3 ** 2)
+    assert abs(bd.phase_window(geom) - (0.5 + 2 * 100.0 * h)) < 1e-12
+    # anisotropic pitch: each axis's half-extent uses its own pitch (3.5, 3.5, 1.5 pitches)
+    geom["pitch"] = np.array([2e-3, 3e-3, 4e-3])
+    h = np.sqrt((3.5 * 2e-3) ** 2 + (3.5 * 3e-3) ** 2 + (1.5 * 4e-3) ** 2)
+    assert abs(bd.phase_window(geom) - (0.5 + 2 * 100.0 * h)) < 1e-12
+    # only the highest frequency matters, whatever the order
+    geom["freq"] = np.array([30e9, 20e9, 25e9])
+    assert abs(bd.phase_window(geom) - (0.5 + 2 * 100.0 * h)) < 1e-12
+    g, keep = bd.make_geometry_struct(geom)
+    assert lib.spgm_phase_window(C.byref(g), None) == bd.SPGM_E_INVALID
+    assert lib.spgm_phase_window(None, C.byref(C.c_double())) == bd.SPGM_E_INVALID
+    geom["c"] = 0.0
+    g, keep = bd.make_geometry_struct(geom)
+    assert lib.spgm_phase_window(C.byref(g), C.byref(C.c_double())) == bd.SPGM_E_INVALID
+
+
+@pytest.mark.parametrize("name", ["c0", "c1", "c2", "c4"])
+def test_benchmark_geometries_fit_the_compensated_window(lib, name):
+    assert bd.phase_window(W.config_geometry(name)) <= bd.COMP32_WINDOW_TURNS
+
+
+def test_compensated_plan_refused_beyond_the_window(lib):
+    """7.5 mm pitch at 30 GHz: 0.5 + 2 * 100 * sqrt(2 (26.25 mm)^2 + (11.25 mm)^2) = 8.26 turns,
+    beyond the 8-turn window: COMP32 plans are refused on the host (before any device call);
+    the float64-phase policy is not (it then needs a device)."""
+    geom = W.make_geometry(8, 8, 4, (20e9, 30e9), (16, 16, 8), 7.5e-3, 0.25, 0.2, seed=1)
+    assert bd.phase_window(geom) > bd.COMP32_WINDOW_TURNS
+    rc, _ = _create(lib, geom, mode=bd.PHASE_COMP32)
+    assert rc == bd.SPGM_E_UNSUPPORTED
+    assert b"SPGM_PHASE_F64" in lib.spgm_last_error()
+    rc, h = _create(lib, geom, mode=bd.PHASE_F64)
+    assert rc != bd.SPGM_E_UNSUPPORTED
+    if rc == bd.SPGM_OK:
+        lib.spgm_plan_destroy(h)

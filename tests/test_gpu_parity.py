@@ -271,3 +271,24 @@ def test_c2_precision_study(bd):
     for mode, (ef, ea) in errs.items():
         assert ef <= PHASE_TOL[mode] and ea <= PHASE_TOL[mode], (PHASE_NAME[mode], ef, ea)
     assert max(errs[1]) < max(errs[0]) < max(errs[2])
+
+
+def test_f64_plan_beyond_the_compensated_window(bd):
+    """7.5 mm pitch at 30 GHz: the compensated float32 argument can reach 8.26 turns, past the
+    window its accuracy holds in, so COMP32 plans are refused; the float64-phase policy (full
+    phase reduced in float64) still matches the oracle to its 1e-6 bound (Sec. II, Eq. 2)."""
+    geom = W.make_geometry(8, 8, 16, (20e9, 30e9), (16, 16, 8), 7.5e-3, 0.25, 0.2, seed=77)
+    assert bd.phase_window(geom) > bd.COMP32_WINDOW_TURNS
+    with pytest.raises(bd.SpgmError) as exc:
+        bd.Plan(geom, phase_mode=bd.PHASE_COMP32)
+    assert exc.value.code == bd.SPGM_E_UNSUPPORTED
+    orc = Oracle(geom)
+    plan = bd.Plan(geom, phase_mode=bd.PHASE_F64)
+    rows = W.draw_rows(orc.M, 256, 1, seed=78)[0]
+    s = W.random_complex(orc.N, seed=79).astype(np.complex64)
+    r = W.random_complex(rows.size, seed=80).astype(np.complex64)
+    ef = rel_l2(host(plan.forward(idev(rows), cdev(s))), orc.forward(rows, s.astype(np.complex128)))
+    ea = rel_l2(host(plan.adjoint(idev(rows), cdev(r))), orc.adjoint(rows, r.astype(np.complex128)))
+    plan.close()
+    say("7.5 mm at 30 GHz, f64 phase: forward %.3e adjoint %.3e" % (ef, ea))
+    assert ef <= PHASE_TOL[1] and ea <= PHASE_TOL[1]
