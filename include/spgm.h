@@ -178,8 +178,9 @@ int spgm_unrolled_vjp_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, co
  * later call of this plan with this B.  Results are cached in a JSON file (cache_path, else the
  * environment variable SPGM_TUNE_CACHE, else no file) keyed by GPU architecture, phase mode,
  * T, R, F, grid and B; a cached key is applied without timing.  Writes the chosen splits to
- * *fwd_splits / *adj_splits (either may be NULL).  Synchronous; allocates temporary device
- * memory.  The adjoint's summation order depends on its split, so results may differ from an
+ * *fwd_splits / *adj_splits (either may be NULL).  Synchronous: first waits for all work on the
+ * plan's device (the timing rewrites the plan's workspace); allocates temporary device memory.
+ * The adjoint's summation order depends on its split, so results may differ from an
  * untuned plan in the last bits (within the parity tolerance). */
 int spgm_plan_autotune(spgm_plan *plan, int32_t B, const char *cache_path, int32_t *fwd_splits,
                        int32_t *adj_splits);
@@ -318,10 +319,19 @@ int spgm_batch_plan(spgm_batch *batch, int32_t i, spgm_plan **plan);
  * rows_d[i][k*B[i] ...]); y_d[i] device complex64[M_i]; s_d[i] device complex64[N_i] in/out;
  * eta[i] > 0, alpha[i] >= 0.  use_graph != 0 captures the launches of the whole solve into a
  * HIP graph and launches it once (one submission; same results).  Grows the batch's workspace
- * with hipMalloc when needed. */
+ * with hipMalloc when needed.  Waits for earlier work on `stream` before rewriting the batch's
+ * descriptors; calls on one batch must not overlap on different streams. */
 int spgm_batch_solve(spgm_batch *batch, int32_t iters, const int32_t *B, const int32_t *const *rows_d,
                      const void *const *y_d, void *const *s_d, const float *eta, const float *alpha,
                      int32_t use_graph, void *stream);
+
+/* Launch shape of spgm_batch_solve's tile phases, kept for later solves of this batch.
+ * max_workgroups caps the persistent grid that walks the (scene, brick, row range) work list
+ * (0: as many work-groups as fit on the chip at once, the default); the result does not depend
+ * on it, bit for bit.  rows_per_split is the length of a work item's row range: scene i's
+ * minibatch is cut into ceil(B[i] / rows_per_split) ranges whose column partials are summed in
+ * range order (0: 1024, the default; otherwise a positive multiple of 64).  Host only. */
+int spgm_batch_options(spgm_batch *batch, int32_t max_workgroups, int32_t rows_per_split);
 
 /* Device-detected row errors of the batch's earlier solves (as spgm_plan_status). */
 int spgm_batch_status(spgm_batch *batch, int32_t *status);

@@ -41,7 +41,7 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched",
             "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured",
             "spgm_prox", "spgm_step_reg", "spgm_solve_reg", "spgm_phase_window",
-            "spgm_solve_tol")
+            "spgm_solve_tol", "spgm_batch_options")
 
 _dp = C.POINTER(C.c_double)
 
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "spgm_step_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, vp, vp, f32, f32, vp],
         "spgm_solve_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_phase_window": [C.POINTER(SpgmGeometry), C.POINTER(C.c_double)],
+        "spgm_batch_options": [vp, i32, i32],
         "spgm_solve_tol": [vp, vp, i32, i32, vp, vp, f32, f32, C.c_double, i32, i32, C.POINTER(i32),
                            C.POINTER(C.c_double), vp],
     }
@@ -533,6 +534,11 @@ class Batch:
         _check(self._lib.spgm_batch_solve(self._h, iters, Bs, rp, yp, sp, ea, aa, 1 if use_graph else 0,
                                           _stream_ptr(stream)))
 
+    def spgm_batch_options(self, max_workgroups=0, rows_per_split=0):
+        """Launch shape of the tile phases: persistent work-groups (0: fill the chip) and rows per
+        work item (0: 1024; else a multiple of 64)."""
+        _check(self._lib.spgm_batch_options(self._h, int(max_workgroups), int(rows_per_split)))
+
     def spgm_batch_status(self):
         st = C.c_int32()
         _check(self._lib.spgm_batch_status(self._h, C.byref(st)))
@@ -540,3 +546,4 @@ class Batch:
 
     solve = spgm_batch_solve
     status = spgm_batch_status
+    options = spgm_batch_options

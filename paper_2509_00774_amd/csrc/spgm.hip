@@ -1295,6 +1295,8 @@ struct spgm_plan {
 };
 
 // A batch of independent scenes (one plan each) advanced together.
+constexpr int kBatchRowsPerSplit = 1024;  // default row range of a ragged-batch work item
+
 struct spgm_batch {
     int device = 0;
     int phase_mode = 0;
@@ -1309,6 +1311,10 @@ struct spgm_batch {
     size_t blocks_cap = 0;
     char *d_ws = nullptr;
     size_t ws_cap = 0;
+    // launch shape of the tile phases: persistent work-groups (0: fill the chip) and rows per
+    // work item
+    int max_wg = 0;
+    int rows_per_split = kBatchRowsPerSplit;
 };
 
 namespace {
@@ -2605,6 +2611,9 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
     if (!p) return fail(SPGM_E_INVALID, "spgm_plan_autotune: plan is NULL");
     if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm_plan_autotune: B=%d outside [1, %d]", B, kMaxB);
     DeviceGuard guard(p->device);
+    // The timing runs on a stream of its own and rewrites the plan's workspace: work queued
+    // earlier on any stream may still use it.
+    if (hipDeviceSynchronize() != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_autotune: device error");
     std::string path = cache_path ? cache_path : "";
     if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
     const std::string key = tune_key(p, B);
@@ -2814,6 +2823,10 @@ int spgm_batch_solve(spgm_batch *b, int32_t iters, const int32_t *B, const int32
     }
     if (iters == 0) return ok();
     DeviceGuard guard(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    // The descriptors, work list and workspace below are rewritten on the host: earlier solves
+    // queued on the caller's stream may still read them.
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_batch_solve: stream error");
     // Layout of the scenes' workspace and the work list.
     std::vector<SceneDev> h(n);
     std::vector<size_t> off(n);
@@ -2833,7 +2846,7 @@ int spgm_batch_solve(spgm_batch *b, int32_t iters, const int32_t *B, const int32
         SceneDev &d = h[i];
         d.geo = p->geo;
         d.B = B[i];
-        d.splits = std::max(1, (B[i] + 1023) / 1024);
+        d.splits = std::max(1, (B[i] + b->rows_per_split - 1) / b->rows_per_split);
         d.rpw = (B[i] + d.splits - 1) / d.splits;
         d.n_tiles = p->n_tiles;
         d.N = (int)p->N;
@@ -2879,7 +2892,6 @@ int spgm_batch_solve(spgm_batch *b, int32_t iters, const int32_t *B, const int32
     }
     std::vector<int2> blocks(rblocks);
     blocks.insert(blocks.end(), cblocks.begin(), cblocks.end());
-    hipStream_t st = (hipStream_t)stream;
     // descriptors and lists are uploaded synchronously, ahead of any (captured) launch
     if (hipMemcpy(b->d_scenes, h.data(), sizeof(SceneDev) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_items, hitems.data(), sizeof(int4) * hitems.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -2895,7 +2907,8 @@ int spgm_batch_solve(spgm_batch *b, int32_t iters, const int32_t *B, const int32
     // persistent grid: as many work-groups as fit on the chip at once
     const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
     const int n_items = (int)hitems.size();
-    const int grid_items = std::max(1, std::min(n_items, 256 * per_cu));
+    const int fill = b->max_wg > 0 ? b->max_wg : 256 * per_cu;
+    const int grid_items = std::max(1, std::min(n_items, fill));
     const int n_rb = (int)rblocks.size(), n_cb = (int)cblocks.size();
     if (!use_graph) {
         if ((rc = batch_launches(b, iters, n_items, grid_items, lds, max_chunks, p2, n_rb, n_cb, st))) return rc;
@@ -2922,6 +2935,16 @@ int spgm_batch_solve(spgm_batch *b, int32_t iters, const int32_t *B, const int32
     hipGraphExecDestroy(ex);  // safe: destruction is deferred until the launch completes
     hipGraphDestroy(g);
     if (le != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_batch_solve: graph launch failed");
+    return ok();
+}
+
+int spgm_batch_options(spgm_batch *b, int32_t max_workgroups, int32_t rows_per_split) {
+    if (!b) return fail(SPGM_E_INVALID, "spgm_batch_options: batch is NULL");
+    if (max_workgroups < 0) return fail(SPGM_E_INVALID, "spgm_batch_options: max_workgroups must be >= 0");
+    if (rows_per_split < 0 || (rows_per_split > 0 && rows_per_split % kWave != 0))
+        return fail(SPGM_E_INVALID, "spgm_batch_options: rows_per_split must be 0 or a positive multiple of %d", kWave);
+    b->max_wg = max_workgroups;
+    b->rows_per_split = rows_per_split > 0 ? rows_per_split : kBatchRowsPerSplit;
     return ok();
 }
 

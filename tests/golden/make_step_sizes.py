@@ -12,7 +12,8 @@ Marchenko-Pastur law for a B x N matrix of independent entries of variance sigma
 sigma^2 (1 + sqrt(N/B))^2, with sigma^2 the mean |A_mn|^2 of oracle rows, scaled by the ratio
 of the power-iteration L to that edge on the mid-size workload c1 (neighbouring voxels give
 correlated columns, which raise the top eigenvalue above the independent-entry edge) and by a
-margin of 1.5.  Its lambda_max is taken over a seeded 1 % voxel sample of A^H y.
+margin of 1.5.  Its lambda_max is taken over a seeded 1 % voxel sample of A^H y.  The 96 scenes
+of the ragged batch (c3) take the same two estimates scene by scene.
 
 Calls only the oracle and the seeded input generators.  Usage:
     python tests/golden/make_step_sizes.py [workload ...]
@@ -68,12 +69,31 @@ def large_case(name, data, t0):
     print(name, data[name], "%.1fs" % (time.time() - t0), flush=True)
 
 
+def ragged_case(name, data, t0):
+    """Per scene of the ragged batch: eta from the scaled independent-entry edge (as for c2) and
+    lambda = 0.05 lambda_max over a seeded 1 % voxel sample, y from the oracle."""
+    ratio = data["c1"]["L"] / mp_edge(Oracle(W.config_geometry("c1")), W.CONFIGS["c1"]["B"])
+    out = []
+    for i, sc in enumerate(W.ragged_scenes()):
+        orc = Oracle(sc["geom"])
+        st, idx = W.random_scene(sc["N"], sc["density"], seed=sc["seed"] + 1)
+        y = W.add_noise(orc.forward_sparse(np.arange(orc.M), idx, st[idx]), sc["snr_db"], seed=sc["seed"] + 2)
+        vox = W.voxel_sample(orc.N, 0.01, seed=sc["seed"] + 9)
+        lam_max = float(np.max(np.abs(orc.adjoint_voxels(np.arange(orc.M), y, vox))) / orc.M)
+        L = 1.5 * ratio * mp_edge(orc, sc["B"])
+        out.append({"eta": 1.0 / L, "lambda": 0.05 * lam_max, "lambda_max": lam_max, "L": L})
+    data[name] = {"scenes": out, "L_mp_ratio_c1": ratio,
+                  "note": "per scene: L = 1.5 x (c1 power-iteration L / c1 independent-entry edge) x "
+                          "sigma^2 (1 + sqrt(N/B))^2; lambda_max = max|A^H y|/M over a seeded 1% voxel sample"}
+    print(name, len(out), "scenes", "%.1fs" % (time.time() - t0), flush=True)
+
+
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         t0 = time.time()
-        if name == "c2":
-            large_case(name, data, t0)
+        if name in ("c2", "c3"):
+            (large_case if name == "c2" else ragged_case)(name, data, t0)
             json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
             continue
         cfg = W.CONFIGS[name]
