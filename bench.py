@@ -17,6 +17,8 @@ Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--workload c2]
                          frequencies, 128x128x64 voxels, B = 16384
        --workload c1     mid-size: 32 Tx + 32 Rx, 64 frequencies, 64x64x32 voxels, B = 4096
        --workload c3     ragged batch of 96 scenes
+       --workload c4grad forward + backward of a 10-iteration unrolled SPGM (learnable steps)
+       --workload calib  measured issue rates of FMA, sin, cos and the entry body (roofline inputs)
        --workload c1k32  32 scenes of the c1 geometry through the shared-geometry batched path
        --workload c1s    c1 geometry with structured (16 f x 16 Tx x 16 Rx) minibatches
        --workload c1tv   c1 with the magnitude-TV prox (10 dual iterations per step) on a blocky scene
@@ -64,13 +66,13 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel, workload, splits=None):
-    """HBM bytes per launch from the committed counter runs (per row split for the tile kernels),
-    if the kernel source is unchanged."""
+def stored_traffic(kernel, workload, shape=None):
+    """HBM bytes per launch from the committed counter runs (per launch shape, row splits and
+    waves per work-group, for the tile kernels), if the kernel source is unchanged."""
     if not os.path.exists(TRAFFIC):
         return None
     data = json.load(open(TRAFFIC))
-    key = "%s/%s" % (kernel, workload) + ("/splits%d" % splits if splits else "")
+    key = "%s/%s" % (kernel, workload) + ("/splits%d/waves%d" % tuple(shape) if shape else "")
     rec = data.get(key)
     if not rec or rec.get("source_sha") != source_sha():
         return None
@@ -110,16 +112,17 @@ def timed_solve(args, torch, plan, timed_rows, y, s, eta, alpha):
     return t1 - t0, fwd_ms, fwd_n, adj_ms, adj_n
 
 
-def alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, splits, wl, phase):
+def alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, phase):
     """Roofline record of the slower tile kernel: VALU issue slots per launch (entries x the
-    9-slot minimum per entry) over its average HIP-event duration, against the issue ceiling."""
+    9-slot minimum per entry) over its average HIP-event duration, against the issue ceiling.
+    shapes: ((forward splits, waves), (adjoint splits, waves)) of the timed launches."""
     fwd_avg = fwd_ms / max(fwd_n, 1) * 1e-3
     adj_avg = adj_ms / max(adj_n, 1) * 1e-3
     kname, kavg = ("k_fwd_tile", fwd_avg) if fwd_avg >= adj_avg else ("k_adj_tile", adj_avg)
     achieved = entries * SLOTS_PER_ENTRY / kavg / 1e12
     peak = VALU_SLOTS_PER_S / 1e12
-    kspl = None if splits is None else splits[0 if kname == "k_fwd_tile" else 1]
-    traffic = stored_traffic(kname, wl, kspl) if phase == "comp32" and kspl else None
+    kshape = shapes[0 if kname == "k_fwd_tile" else 1]
+    traffic = stored_traffic(kname, wl, kshape) if phase == "comp32" else None
     return {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
             "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": traffic,
             "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
@@ -193,7 +196,8 @@ def bench_large(args, torch, binding, dev):
     log("timed %d steps in %.4f s (%.4f ms/step); forward tile %.4f ms avg over %d, adjoint tile %.4f ms avg over %d" % (
         K, dt, 1e3 * dt / K, fwd_ms / max(fwd_n, 1), fwd_n, adj_ms / max(adj_n, 1), adj_n))
     entries = float(B) * N
-    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, splits, wl, args.phase)
+    shapes = plan.spgm_plan_launch_shape(B)
+    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, args.phase)
 
     cpu = None
     par = {}
@@ -241,7 +245,9 @@ def bench_large(args, torch, binding, dev):
         "config": {"workload": "c2: %d Tx + %d Rx, %d frequencies, %dx%dx%d voxels, B=%d rows per minibatch, "
                                "points plus three planar patches" % (cfg["T"], cfg["R"], cfg["F"], *cfg["grid"], B),
                    "M": M, "N": N, "B": B, "hip_graph": not args.eager,
-                   "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]},
+                   "launch_shape": {"forward": {"splits": shapes[0][0], "waves": shapes[0][1]},
+                                    "adjoint": {"splits": shapes[1][0], "waves": shapes[1][1]},
+                                    "autotuned": splits is not None},
                    "phase": PHASE_DESC[args.phase]},
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if not par else float("%.3e" % max(
@@ -260,7 +266,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c0", "c1", "c4", "c3", "c1k32", "c1s", "c1tv"],
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c0", "c1", "c4", "c3", "c1k32", "c1s", "c1tv", "c4grad", "calib"],
                     help="c2 (default) is the largest single-GPU configuration; c3 is the ragged batch of 96 "
                          "scenes advanced together")
     ap.add_argument("--cpu-iters", type=int, default=5, help="iterations of the oracle timed on the host")
@@ -299,6 +306,10 @@ def main():
         return bench_large(args, torch, binding, dev)
     if wl == "c3":
         return bench_ragged(args, torch, binding, dev)
+    if wl == "c4grad":
+        return bench_unrolled(args, torch, binding, dev)
+    if wl == "calib":
+        return bench_calibrate(args, binding)
     if wl == "c1k32":
         return bench_batched(args, torch, binding, dev)
     if wl == "c1s":
@@ -353,7 +364,8 @@ def main():
 
     entries = float(B) * N
     value = entries * K / dt / 1e9
-    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, splits, wl, args.phase)
+    shapes = plan.spgm_plan_launch_shape(B)
+    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, args.phase)
 
     cpu = None
     rel_vs_oracle = None
@@ -390,7 +402,9 @@ def main():
         "config": {"workload": "%s: %d Tx + %d Rx, %d frequencies, %dx%dx%d voxels, B=%d rows per minibatch" % (
             wl, cfg["T"], cfg["R"], cfg["F"], *cfg["grid"], B),
             "M": M, "N": N, "B": B, "hip_graph": not args.eager,
-            "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]},
+            "launch_shape": {"forward": {"splits": shapes[0][0], "waves": shapes[0][1]},
+                             "adjoint": {"splits": shapes[1][0], "waves": shapes[1][1]},
+                             "autotuned": splits is not None},
             "phase": PHASE_DESC[args.phase]},
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if rel_vs_oracle is None else float("%.3e" % rel_vs_oracle),
@@ -401,6 +415,124 @@ def main():
     }
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def bench_unrolled(args, torch, binding, dev):
+    """Differentiable unrolled SPGM (16 Tx + 16 Rx, 32 frequencies, 32x32x16 voxels, B = 2048,
+    K = 10 iterations with learnable per-iteration step sizes and thresholds): forward plus
+    backward of the unroll (MSE loss to the true scene), against 10 plain iterations of the
+    float32 solve.  Entries formed per forward + backward: 2 K B N in the forward, 4 K B N in
+    the backward (segment recompute with the kept gradient, then A^H A zbar)."""
+    from paper_2509_00774_amd.autograd import unrolled_spgm
+    cfg = W.CONFIGS["c4"]
+    geom = W.config_geometry("c4")
+    M, N = W.dims(geom)
+    B, K = cfg["B"], cfg["K"]
+    reps, Wm = args.steps, args.warmup
+    sj = json.load(open(STEP_SIZES))["c4"]
+    eta = (sj["eta"] * (1.0 + 0.05 * np.arange(K))).astype(np.float32).astype(np.float64)
+    tau = (sj["lambda"] * eta).astype(np.float32).astype(np.float64)
+    s_true, idx = W.config_scene("c4")
+    rows = W.config_rows("c4", K=K)
+    plan = binding.Plan(geom)
+    splits = None if args.no_tune else plan.spgm_plan_autotune(B)
+    y0 = plan.spgm_forward(torch.arange(M, dtype=torch.int32, device=dev),
+                           torch.from_numpy(s_true.astype(np.complex64)).to(dev))
+    y = torch.from_numpy(W.add_noise(y0.cpu().numpy().astype(np.complex128), cfg["snr_db"],
+                                     seed=cfg["seed"] + 2).astype(np.complex64)).to(dev)
+    rows_d = torch.from_numpy(rows).to(dev)
+    st = torch.from_numpy(s_true.astype(np.complex64)).to(dev)
+
+    def fwd_bwd():
+        s0 = torch.zeros(N, dtype=torch.complex64, device=dev, requires_grad=True)
+        e = torch.tensor(eta, dtype=torch.float64, device=dev, requires_grad=True)
+        t = torch.tensor(tau, dtype=torch.float64, device=dev, requires_grad=True)
+        out = unrolled_spgm(plan, rows_d, y, s0, e, t)
+        loss = torch.mean(torch.abs(out - st) ** 2)
+        loss.backward()
+        return out, s0.grad, e.grad, t.grad
+
+    for _ in range(Wm):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = fwd_bwd()
+    torch.cuda.synchronize()
+    t_fb = (time.perf_counter() - t0) / reps
+    s = torch.zeros(N, dtype=torch.complex64, device=dev)
+    plan.spgm_solve(rows_d, y, s, float(eta[0]), float(tau[0]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.spgm_solve(rows_d, y, s, float(eta[0]), float(tau[0]))
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    entries = 6.0 * K * B * N
+    log("unrolled forward + backward: %.3f ms; 10 plain iterations: %.3f ms" % (1e3 * t_fb, 1e3 * t_plain))
+    out, gs0, geta, gtau = (r.detach() for r in res)
+    cpu = None
+    par = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.Oracle(geom)
+        y_h = y.cpu().numpy().astype(np.complex128)
+        log("oracle: unrolled forward and chain rule in FP64 on %d threads" % oracle.num_threads())
+        c0 = time.perf_counter()
+        it = oracle.unrolled_forward(orc, rows, y_h, np.zeros(N), eta, tau)
+        sbar = 2.0 * (it[-1] - s_true.astype(np.complex64).astype(np.complex128)) / N
+        s0bar, eta_bar, tau_bar = oracle.unrolled_vjp(orc, rows, y_h, it, eta, tau, sbar)
+        c1 = time.perf_counter()
+        par = {"s_K": oracle.rel_l2(out.cpu().numpy(), it[-1]), "d_s0": oracle.rel_l2(gs0.cpu().numpy(), s0bar),
+               "d_eta": oracle.rel_l2(geta.cpu().numpy(), eta_bar), "d_tau": oracle.rel_l2(gtau.cpu().numpy(), tau_bar)}
+        cpu = {"value": round(entries / (c1 - c0) / 1e9, 4), "unit": "Gentries/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "one forward + backward of the same 10-iteration unroll (FP64 iterates and chain rule), "
+                         "%.1f s" % (c1 - c0)}
+        log("oracle: %.1f s; parity %s" % (c1 - c0, json.dumps(par)))
+    achieved = entries * SLOTS_PER_ENTRY / t_fb / 1e12
+    peak = VALU_SLOTS_PER_S / 1e12
+    out_line = {
+        "metric": "unrolled SPGM forward + backward Gentries/s (6 K B N entries per pass) against K plain iterations",
+        "value": round(entries / t_fb / 1e9, 2), "unit": "Gentries/s", "n_gpus": 1, "steps": reps, "warmup": Wm,
+        "ms_per_step": round(1e3 * t_fb, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c4grad: 16 Tx + 16 Rx, 32 frequencies, 32x32x16 voxels, B=2048, 10 unrolled iterations "
+                               "with learnable eta_k, tau_k, MSE loss, sqrt(K) checkpoints",
+                   "M": M, "N": N, "B": B, "K": K,
+                   "row_splits": None if splits is None else {"forward": splits[0], "adjoint": splits[1]}},
+        "ms_plain_k_iterations": round(1e3 * t_plain, 4),
+        "fwd_bwd_over_plain": round(t_fb / t_plain, 3),
+        "rel_l2_vs_oracle": None if not par else float("%.3e" % max(par.values())),
+        "parity": {k: float("%.3e" % v) for k, v in par.items()},
+        "roofline": {"bound": "alu", "kernel": "whole forward + backward", "achieved": round(achieved, 3),
+                     "peak": round(peak, 3), "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4),
+                     "traffic": None, "entries_per_pass": int(entries), "slots_per_entry": SLOTS_PER_ENTRY},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out_line), flush=True)
+    plan.close()
+
+
+def bench_calibrate(args, binding):
+    """Issue rates behind the VALU roofline: v_fma_f32, v_sin_f32, v_cos_f32 and the entry body
+    (phase FMA, sin, cos, four FMAs), each the best of five launches of the library's probe."""
+    names = ["fma", "sin", "cos", "entry_body"]
+    rates = {}
+    for kind, name in enumerate(names):
+        best = max(binding.calibrate(kind, 4096)[0] for _ in range(5))
+        rates[name] = best
+        log("%s: %.3f T chain steps/s" % (name, best / 1e12))
+    fma = rates["fma"]
+    out = {"metric": "VALU issue rates (T lane-ops/s)", "value": round(rates["entry_body"] / 1e12, 4),
+           "unit": "T entry bodies/s", "n_gpus": 1, "steps": 5, "warmup": 1, "higher_is_better": True,
+           "config": {"workload": "calib: 8 work-groups of 256 threads per compute unit, 8 independent chains per lane"},
+           "rates_T_per_s": {k: round(v / 1e12, 3) for k, v in rates.items()},
+           "issue_ceiling_T_slots_per_s": round(VALU_SLOTS_PER_S / 1e12, 3),
+           "fma_fraction_of_ceiling": round(fma / VALU_SLOTS_PER_S, 4),
+           "sin_slots": round(fma / rates["sin"], 3), "cos_slots": round(fma / rates["cos"], 3),
+           "entry_body_slots": round(fma / rates["entry_body"], 3)}
+    print(json.dumps(out), flush=True)
 
 
 def bench_ragged(args, torch, binding, dev):
@@ -830,8 +962,8 @@ def bench_tv(args, torch, binding, dev):
         "rel_l2_vs_oracle_after_iters": n_par,
         "roofline": {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
                      "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4),
-                     "traffic": None if splits is None else stored_traffic(
-                         kname, "c1tv", splits[0 if kname == "k_fwd_tile" else 1]),
+                     "traffic": stored_traffic(kname, "c1tv",
+                                               plan.spgm_plan_launch_shape(B)[0 if kname == "k_fwd_tile" else 1]),
                      "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
                      "avg_launch_ms": round(kavg * 1e3, 5), "fwd_tile_ms": round(fwd_avg * 1e3, 5),
                      "adj_tile_ms": round(adj_avg * 1e3, 5)},

@@ -120,6 +120,14 @@ int spgm_adjoint(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *
 int spgm_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d, void *s_d,
               float eta, float alpha, void *stream);
 
+/* spgm_step that also writes g_d = A_B^H (A_B s - y_B) at the entering iterate (unscaled, the
+ * minibatch gradient of Eq. 6 times B; complex64[N], must not alias s_d): the quantity the
+ * backward of an unrolled iteration needs, formed by the same column reduction.  The update
+ * of s_d is bitwise that of spgm_step. */
+int spgm_step_grad(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d, void *s_d,
+                   float eta, float alpha, void *g_d, void *stream);
+
+
 /* `iters` SPGM iterations; iteration k uses rows_d[k*B .. k*B + B - 1] (rows_d: int32[iters*B]).
  * Bitwise equal to `iters` calls of spgm_step.  iters >= 0.  Intermediate iterates alternate
  * between s_d and a plan-owned buffer of N complex64 (allocated on the first solve); s_d holds
@@ -172,10 +180,20 @@ int spgm_unrolled_vjp_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, co
                            const void *s_d, float eta, float tau, const void *sbar_next_d,
                            void *sbar_d, double *eta_bar_d, double *tau_bar_d, void *stream);
 
+/* spgm_unrolled_vjp_step given the gradient at the entering iterate instead of y:
+ * g_d = A_B^H (A_B s - y_B) (unscaled, complex64[N], e.g. from spgm_step_grad when the iterate
+ * was recomputed), so only A_B^H A_B zbar forms entries (two passes instead of four).  Same
+ * outputs, bit for bit, as spgm_unrolled_vjp_step with the y that gives this g. */
+int spgm_unrolled_vjp_step_g(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *s_d,
+                             const void *g_d, float eta, float tau, const void *sbar_next_d,
+                             void *sbar_d, double *eta_bar_d, double *tau_bar_d, void *stream);
+
 /* Autotuner.  For minibatch size B, times the forward-tile and adjoint-tile kernels over the
- * candidate row splits (rows of the minibatch per work-group: splits 1, 2, 3, 4, 6, 8, ... up to
- * ceil(B/64)) on uniform pseudo-random rows, and keeps the fastest split per kernel for every
- * later call of this plan with this B.  Results are cached in a JSON file (cache_path, else the
+ * candidate launch shapes -- row splits (rows of the minibatch per work-group: splits 1, 2, 3, 4,
+ * 6, 8, ... up to ceil(B/64)) times 8 or 16 waves per work-group (16 only where its LDS fits) --
+ * on uniform pseudo-random rows, and keeps the fastest shape per kernel for every later call of
+ * this plan with this B.  Without tuning, a plan uses 8 waves where two work-groups fit in one
+ * compute unit's LDS and 16 otherwise (four waves per SIMD either way).  Results are cached in a JSON file (cache_path, else the
  * environment variable SPGM_TUNE_CACHE, else no file) keyed by GPU architecture, phase mode,
  * T, R, F, grid and B; a cached key is applied without timing.  Writes the chosen splits to
  * *fwd_splits / *adj_splits (either may be NULL).  Synchronous: first waits for all work on the
@@ -184,6 +202,12 @@ int spgm_unrolled_vjp_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, co
  * untuned plan in the last bits (within the parity tolerance). */
 int spgm_plan_autotune(spgm_plan *plan, int32_t B, const char *cache_path, int32_t *fwd_splits,
                        int32_t *adj_splits);
+
+/* Launch shape the tile kernels use for minibatches of B rows on this plan (the autotuned one,
+ * else the default): row splits and waves per work-group of the forward and adjoint tile
+ * kernels.  Any output pointer may be NULL.  Host only. */
+int spgm_plan_launch_shape(const spgm_plan *plan, int32_t B, int32_t *fwd_splits, int32_t *fwd_waves,
+                           int32_t *adj_splits, int32_t *adj_waves);
 
 /* Shared-geometry batches: K right-hand sides (K images of one scene geometry, or K
  * measurement sets) through one set of entries of the minibatch.  Every entry of A_B is
@@ -349,6 +373,16 @@ int spgm_plan_status(spgm_plan *plan, int32_t *status);
 int spgm_plan_timing(spgm_plan *plan, int32_t enable);
 int spgm_plan_timing_read(spgm_plan *plan, double *fwd_ms, int64_t *fwd_launches, double *adj_ms,
                           int64_t *adj_launches);
+
+/* Issue-rate probe for the rooflines of the entry-generating kernels, on the current device.
+ * One launch of 8 work-groups of 256 threads per compute unit, each lane running `iters`
+ * rounds of 8 independent dependency chains of: kind 0, v_fma_f32; kind 1, v_sin_f32; kind 2,
+ * v_cos_f32; kind 3, the entry body of the tile kernels (one phase FMA, sin, cos and four FMAs
+ * of the complex multiply-add).  Writes the chain steps per second over all lanes
+ * (*ops_per_s: lane-instructions/s for kinds 0-2, entry bodies/s for kind 3) and the launch
+ * time (*ms, may be NULL), timed with HIP events after one warm-up launch.  Synchronous;
+ * allocates a small device buffer. */
+int spgm_calibrate(int32_t kind, int32_t iters, double *ops_per_s, double *ms);
 
 /* Message describing the last failure of a call on this thread ("" if none). */
 const char *spgm_last_error(void);

@@ -7,9 +7,10 @@
   per-iteration step sizes ``eta_k`` and thresholds ``tau_k`` as differentiable parameters:
       s_{k+1} = S_{tau_k}( s_k - (eta_k/B) A_k^H (A_k s_k - y_k) ).
   The forward pass keeps only checkpoints of the iterate (every ``checkpoint_every``
-  iterations, default ceil(sqrt(K))); the backward pass recomputes the iterates of one segment
-  at a time and runs the native backward step ``spgm_unrolled_vjp_step`` (which regenerates
-  the matrix entries it needs), so memory is O(sqrt(K) N) instead of O(K N).
+  iterations, default ceil(sqrt(K))); the backward pass recomputes one segment at a time with
+  ``spgm_step_grad`` (the iterate and the gradient A_k^H (A_k s_k - y_k) at it) and runs the
+  native backward step ``spgm_unrolled_vjp_step_g``, which forms entries only for
+  A_k^H A_k zbar: four entry passes per iteration, and O(sqrt(K) N) memory instead of O(K N).
 
 Complex gradients follow PyTorch's convention for real losses (dL/dRe + j dL/dIm).  Tensors
 are complex64 / int32 on the plan's device; every arithmetic step runs in the library.
@@ -91,15 +92,19 @@ class UnrolledSPGMFn(torch.autograd.Function):
         tau_bar = torch.zeros(K, dtype=torch.float64, device=dev)
         for start in sorted(ctx.ckpts, reverse=True):
             end = min(K, start + c)
-            # recompute the iterates s_start .. s_{end-1} of this segment
-            states = [ctx.ckpts[start]]
-            for k in range(start, end - 1):
+            # recompute the iterates s_start .. s_{end-1} of this segment and the gradient
+            # A_k^H (A_k s_k - y_k) at each of them (the last step's new iterate is not needed)
+            states, grads = [ctx.ckpts[start]], []
+            for k in range(start, end):
                 nxt = states[-1].clone()
-                plan.spgm_step(rows[k], y, nxt, ctx.eta_h[k], ctx.tau_h[k])
-                states.append(nxt)
+                g = torch.empty_like(nxt)
+                plan.spgm_step_grad(rows[k], y, nxt, ctx.eta_h[k], ctx.tau_h[k], g)
+                grads.append(g)
+                if k + 1 < end:
+                    states.append(nxt)
             for k in range(end - 1, start - 1, -1):
-                plan.spgm_unrolled_vjp_step(rows[k], y, states[k - start], ctx.eta_h[k], ctx.tau_h[k], sbar, sbar,
-                                            eta_bar[k:k + 1], tau_bar[k:k + 1])
+                plan.spgm_unrolled_vjp_step_g(rows[k], states[k - start], grads[k - start], ctx.eta_h[k],
+                                              ctx.tau_h[k], sbar, sbar, eta_bar[k:k + 1], tau_bar[k:k + 1])
         edt, edev, tdt, tdev = ctx.param_meta
         return None, sbar, eta_bar.to(dtype=edt, device=edev), tau_bar.to(dtype=tdt, device=tdev), None, None, None
 

@@ -41,7 +41,8 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched",
             "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured",
             "spgm_prox", "spgm_step_reg", "spgm_solve_reg", "spgm_phase_window",
-            "spgm_solve_tol", "spgm_batch_options")
+            "spgm_solve_tol", "spgm_batch_options", "spgm_step_grad",
+            "spgm_unrolled_vjp_step_g", "spgm_plan_launch_shape", "spgm_calibrate")
 
 _dp = C.POINTER(C.c_double)
 
@@ -116,6 +117,10 @@ def load_library(path: str = LIB_PATH):
         "spgm_solve_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_phase_window": [C.POINTER(SpgmGeometry), C.POINTER(C.c_double)],
         "spgm_batch_options": [vp, i32, i32],
+        "spgm_step_grad": [vp, vp, i32, vp, vp, f32, f32, vp, vp],
+        "spgm_plan_launch_shape": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "spgm_calibrate": [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "spgm_unrolled_vjp_step_g": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
         "spgm_solve_tol": [vp, vp, i32, i32, vp, vp, f32, f32, C.c_double, i32, i32, C.POINTER(i32),
                            C.POINTER(C.c_double), vp],
     }
@@ -166,6 +171,14 @@ def phase_window(geom):
     _check(load_library().spgm_phase_window(C.byref(g), C.byref(out)))
     del keep
     return out.value
+
+
+def calibrate(kind, iters=4096):
+    """(chain steps per second, launch ms) of the issue-rate probe `kind` (0 FMA, 1 sin, 2 cos,
+    3 entry body) on the current device."""
+    rate, ms = C.c_double(), C.c_double()
+    _check(load_library().spgm_calibrate(int(kind), int(iters), C.byref(rate), C.byref(ms)))
+    return rate.value, ms.value
 
 
 def _stream_ptr(stream):
@@ -328,6 +341,28 @@ class Plan:
             _stream_ptr(stream)))
         return sbar
 
+    def spgm_unrolled_vjp_step_g(self, rows, s, g, eta, tau, sbar_next, sbar, eta_bar, tau_bar, stream=None):
+        """spgm_unrolled_vjp_step given g = A_B^H (A_B s - y_B) at the entering iterate."""
+        import torch
+        B = rows.numel()
+        _check(self._lib.spgm_unrolled_vjp_step_g(
+            self._h, _dev(rows, torch.int32, "rows"), B, _dev(s, torch.complex64, "s", self.N),
+            _dev(g, torch.complex64, "g", self.N), float(eta), float(tau),
+            _dev(sbar_next, torch.complex64, "sbar_next", self.N), _dev(sbar, torch.complex64, "sbar", self.N),
+            _dev(eta_bar, torch.float64, "eta_bar", 1), _dev(tau_bar, torch.float64, "tau_bar", 1),
+            _stream_ptr(stream)))
+        return sbar
+
+    def spgm_step_grad(self, rows, y, s, eta, alpha, g, stream=None):
+        """spgm_step that also writes g = A_B^H (A_B s - y_B) at the entering iterate."""
+        import torch
+        B = rows.numel()
+        _check(self._lib.spgm_step_grad(self._h, _dev(rows, torch.int32, "rows"), B,
+                                        _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
+                                        float(eta), float(alpha), _dev(g, torch.complex64, "g", self.N),
+                                        _stream_ptr(stream)))
+        return s
+
     def spgm_solve_graph(self, rows_table, y, s, eta, alpha, stream=None):
         """spgm_solve replayed from a captured HIP graph (re-captured when arguments change)."""
         import torch
@@ -346,6 +381,12 @@ class Plan:
         path = None if cache_path is None else os.fsencode(cache_path)
         _check(self._lib.spgm_plan_autotune(self._h, int(B), path, C.byref(fs), C.byref(as_)))
         return fs.value, as_.value
+
+    def spgm_plan_launch_shape(self, B):
+        """((forward splits, waves), (adjoint splits, waves)) used for minibatches of B rows."""
+        v = [C.c_int32() for _ in range(4)]
+        _check(self._lib.spgm_plan_launch_shape(self._h, int(B), *[C.byref(x) for x in v]))
+        return (v[0].value, v[1].value), (v[2].value, v[3].value)
 
     def spgm_plan_status(self):
         st = C.c_int32()

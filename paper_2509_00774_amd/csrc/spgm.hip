@@ -266,7 +266,10 @@ __device__ __forceinline__ int row_l(int w) { return (w >> 12) & 0xfff; }
 
 constexpr size_t kAntBytes = 32;  // LDS bytes per antenna (largest policy)
 
+// LDS carve-up of a tile work-group of W waves (W x 64 rows staged per sub-chunk).
+template <int W = kWaves>
 __device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
+    constexpr int sub = W * kWave;
     TileSmem t;
     const int A = g.T + g.R;
     t.antg = reinterpret_cast<float4 *>(smem);
@@ -274,8 +277,8 @@ __device__ __forceinline__ TileSmem carve(char *smem, const Geo &g) {
     t.antg64 = reinterpret_cast<double4 *>(smem);
     char *p = smem + kAntBytes * A;
     t.rowinfo = reinterpret_cast<float4 *>(p);
-    t.rowv = reinterpret_cast<float2 *>(t.rowinfo + kSub);
-    t.snew = t.rowv + kSub;
+    t.rowv = reinterpret_cast<float2 *>(t.rowinfo + sub);
+    t.snew = t.rowv + sub;
     t.lside = t.snew + kBrick;
     return t;
 }
@@ -403,12 +406,13 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int
     double cx, cy, cz;
     brick_centre(g, bx, by, bz, cx, cy, cz);
     const int A = g.T + g.R;
-    for (int a = threadIdx.x; a < A; a += kThreads) P::stage_ant(g, sm, a, cx, cy, cz);
+    const int nthr = blockDim.x;  // a multiple of kBrick
+    for (int a = threadIdx.x; a < A; a += nthr) P::stage_ant(g, sm, a, cx, cy, cz);
     if (TABLE && g.ltab && g.ltab_mode == MODE) {
         const int n4 = g.nL * (kBrick / 2);  // float4 per brick table
         const float4 *src = g.ltab + (size_t)((bz * g.nby + by) * g.nbx + bx) * n4;
         float4 *dst = static_cast<float4 *>(sm.lside);
-        for (int i = threadIdx.x; i < n4; i += kThreads) dst[i] = src[i];
+        for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
         return;
     }
     __syncthreads();
@@ -417,7 +421,7 @@ __device__ __forceinline__ void stage_tile(const Geo &g, const TileSmem &sm, int
     const bool inside = bx * kBX + lx < g.nx && by * kBY + ly < g.ny && bz * kBZ + lz < g.nz;
     const typename P::Vox vx = P::vox(g, bx, by, bz, lx, ly, lz);
     typename P::LE *lside = static_cast<typename P::LE *>(sm.lside);
-    for (int li = threadIdx.x / kBrick; li < g.nL; li += kThreads / kBrick) {
+    for (int li = threadIdx.x / kBrick; li < g.nL; li += nthr / kBrick) {
         typename P::D dl = 0;
         float wl = 0.f;
         if (inside) P::geom(sm, ant_of_l(g, li), vx, dl, wl);
@@ -465,8 +469,9 @@ __device__ __forceinline__ void tile_and_split(int &tile, int &split) {
 
 // Each wave owns a contiguous run of the work-group's sorted rows [r0, r1): wave w takes
 // [wb, we), a multiple of 64 rows long, so antenna changes stay as rare as in the sorted order.
+template <int W = kWaves>
 __device__ __forceinline__ void wave_rows(int r0, int r1, int w, int &wb, int &we, int &nsub) {
-    const int per = ((r1 - r0 + kWaves - 1) / kWaves + kWave - 1) / kWave * kWave;
+    const int per = ((r1 - r0 + W - 1) / W + kWave - 1) / kWave * kWave;
     wb = min(r1, r0 + w * per);
     we = min(r1, wb + per);
     nsub = per / kWave;  // sub-chunks of 64 rows per wave (same for every wave)
@@ -481,10 +486,11 @@ struct RowFetch {
     int4 info;
 };
 
+template <int W = kWaves>
 __device__ __forceinline__ RowFetch fetch_rows(const int4 *__restrict__ srt, int r0, int r1, int j) {
     const int t = threadIdx.x;
     int wb, we, nsub;
-    wave_rows(r0, r1, t / kWave, wb, we, nsub);
+    wave_rows<W>(r0, r1, t / kWave, wb, we, nsub);
     RowFetch f;
     f.r = wb + j * kWave + (t % kWave);
     f.pg = f.pl = -1;
@@ -565,13 +571,13 @@ struct SStep {
 // ------------------------------------------------------------------------------------------
 // Body shared by the single-plan launch (one brick x row range per work-group) and the
 // work-list launch over many scenes: brick `tile`, sorted rows [r0, r1).
-template <int MODE>
+template <int MODE, int W = kWaves>
 __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile, int r0, int r1,
                                               const int4 *__restrict__ srt, int B, const float2 *s,
                                               float2 *__restrict__ part, const SStep &up, bool store_s) {
     using P = Phase<MODE>;
     using DT = typename P::D;
-    const TileSmem sm = carve(smem, g);
+    const TileSmem sm = carve<W>(smem, g);
     int bx, by, bz;
     brick_of(g, tile, bx, by, bz);
     // A deferred proximal step: the first four waves form the brick's new iterate (voxel
@@ -621,12 +627,12 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
     for (int q = 0; q < 16; ++q) accr[q] = acci[q] = 0.f;
     const bool b3 = lane & 8, b2 = lane & 4;
     int wb, we, nsub;
-    wave_rows(r0, r1, wave, wb, we, nsub);
+    wave_rows<W>(r0, r1, wave, wb, we, nsub);
     const float4 *rinfo = sm.rowinfo + wave * kWave;
 
     // Every wave stages, reads and stores only its own rows, so after the brick tables are
     // staged the waves run their row loops independently (no work-group barrier per sub-chunk).
-    RowFetch next = fetch_rows(srt, r0, r1, 0);
+    RowFetch next = fetch_rows<W>(srt, r0, r1, 0);
     __syncthreads();  // brick tables (and a deferred step's iterate) staged
     if (deferred) {
 #pragma unroll
@@ -640,7 +646,7 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
         wave_lds_order();  // previous sub-chunk's row data consumed
         const int my_row = stage_fetched<MODE>(g, sm, next);
         wave_lds_order();
-        if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
+        if (j + 1 < nsub) next = fetch_rows<W>(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         // Blocks of 16 consecutive rows, one transposed reduction each.  G-antenna and pair changes
         // are handled at the row where they happen.  Rows of the last block past cnt are formed
@@ -719,14 +725,14 @@ __device__ __forceinline__ void fwd_tile_body(const Geo &g, char *smem, int tile
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
-                                                       const float2 *s, float2 *__restrict__ part, SStep up) {
+template <int MODE, int W>
+__global__ __launch_bounds__(W * 64) void k_fwd_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
+                                                     const float2 *s, float2 *__restrict__ part, SStep up) {
     extern __shared__ __align__(16) char smem[];
     int tile, split;
     tile_and_split(tile, split);
     const int r0 = split * rows_per_wg;
-    fwd_tile_body<MODE>(g, smem, tile, r0, min(B, r0 + rows_per_wg), srt, B, s, part, up, split == 0);
+    fwd_tile_body<MODE, W>(g, smem, tile, r0, min(B, r0 + rows_per_wg), srt, B, s, part, up, split == 0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -821,13 +827,13 @@ __global__ __launch_bounds__(256) void k_gather_scale(Geo g, const int4 *__restr
 //    Rows of one (G, L) pair share the amplitude 1/(d_G d_L) of each voxel, so their terms are
 //    summed first and scaled once when the pair ends.
 // ------------------------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, int W = kWaves>
 __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile, int split, int r0, int r1,
                                               const int4 *__restrict__ srt, int B, const float2 *__restrict__ rs,
                                               float2 *__restrict__ gpart, int N) {
     using P = Phase<MODE>;
     using DT = typename P::D;
-    const TileSmem sm = carve(smem, g);
+    const TileSmem sm = carve<W>(smem, g);
     int bx, by, bz;
     brick_of(g, tile, bx, by, bz);
     stage_tile<MODE>(g, sm, bx, by, bz);
@@ -845,17 +851,17 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
     const typename P::LE *lbase = static_cast<const typename P::LE *>(sm.lside) + lane;
 
     DT dG[kP], D[kP];
-    float wG[kP], W[kP], hr[kP], hi[kP], gr[kP], gi_[kP];
+    float wG[kP], Wpr[kP], hr[kP], hi[kP], gr[kP], gi_[kP];
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
         dG[p] = D[p] = 0;
-        wG[p] = W[p] = hr[p] = hi[p] = gr[p] = gi_[p] = 0.f;
+        wG[p] = Wpr[p] = hr[p] = hi[p] = gr[p] = gi_[p] = 0.f;
     }
     int wb, we, nsub;
-    wave_rows(r0, r1, wave, wb, we, nsub);
+    wave_rows<W>(r0, r1, wave, wb, we, nsub);
     const float4 *rinfo = sm.rowinfo + wave * kWave;
 
-    RowFetch next = fetch_rows(srt, r0, r1, 0);
+    RowFetch next = fetch_rows<W>(srt, r0, r1, 0);
     __syncthreads();  // brick tables staged; from here each wave works on its own rows only
     for (int j = 0; j < nsub; ++j) {
         wave_lds_order();  // previous sub-chunk's row data consumed
@@ -877,7 +883,7 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
         }
         const unsigned long long pairs = __ballot(my_word & kNewPair);
         wave_lds_order();
-        if (j + 1 < nsub) next = fetch_rows(srt, r0, r1, j + 1);
+        if (j + 1 < nsub) next = fetch_rows<W>(srt, r0, r1, j + 1);
         const int cnt = max(0, min(kWave, we - wb - j * kWave));
         // Blocks of 16 rows, unrolled: row entries through one address register with immediate
         // offsets (an opaque zero keeps the base in a VGPR).
@@ -894,8 +900,8 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
                     // close the previous pair and set up the new one
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
-                        gr[p] = fmaf(W[p], hr[p], gr[p]);
-                        gi_[p] = fmaf(W[p], hi[p], gi_[p]);
+                        gr[p] = fmaf(Wpr[p], hr[p], gr[p]);
+                        gi_[p] = fmaf(Wpr[p], hi[p], gi_[p]);
                         hr[p] = hi[p] = 0.f;
                     }
                     if (word & kNewG) {
@@ -914,7 +920,7 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
                     for (int p = 0; p < kP; ++p) {
                         const typename P::LE lv = lp[p * kWave];
                         D[p] = P::pair_d(dG[p], lv);
-                        W[p] = wG[p] * P::lw(lv);
+                        Wpr[p] = wG[p] * P::lw(lv);
                     }
                 }
 #pragma unroll
@@ -933,12 +939,12 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
     }
 #pragma unroll
     for (int p = 0; p < kP; ++p) {
-        gr[p] = fmaf(W[p], hr[p], gr[p]);
-        gi_[p] = fmaf(W[p], hi[p], gi_[p]);
+        gr[p] = fmaf(Wpr[p], hr[p], gr[p]);
+        gi_[p] = fmaf(Wpr[p], hi[p], gi_[p]);
     }
     // Combine the waves in a fixed order.
     __syncthreads();
-    float2 *red = static_cast<float2 *>(sm.lside);  // kWaves x 256 float2, L-side terms no longer needed
+    float2 *red = static_cast<float2 *>(sm.lside);  // W x 256 float2, L-side terms no longer needed
 #pragma unroll
     for (int p = 0; p < kP; ++p) red[wave * kBrick + p * kWave + lane] = make_float2(gr[p], gi_[p]);
     __syncthreads();
@@ -946,7 +952,7 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
     const int ix = bx * kBX + ((v & 63) & 7), iy = by * kBY + ((v & 63) >> 3), iz = bz * kBZ + (v >> 6);
     if (v < kBrick && ix < g.nx && iy < g.ny && iz < g.nz) {
         float2 acc = red[v];
-        for (int w = 1; w < kWaves; ++w) {
+        for (int w = 1; w < W; ++w) {
             acc.x += red[w * kBrick + v].x;
             acc.y += red[w * kBrick + v].y;
         }
@@ -954,15 +960,14 @@ __device__ __forceinline__ void adj_tile_body(const Geo &g, char *smem, int tile
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_adj_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
-                                                       const float2 *__restrict__ rs, float2 *__restrict__ gpart,
-                                                       int N) {
+template <int MODE, int W>
+__global__ __launch_bounds__(W * 64) void k_adj_tile(Geo g, const int4 *__restrict__ srt, int B, int rows_per_wg,
+                                                     const float2 *__restrict__ rs, float2 *__restrict__ gpart, int N) {
     extern __shared__ __align__(16) char smem[];
     int tile, split;
     tile_and_split(tile, split);
     const int r0 = split * rows_per_wg;
-    adj_tile_body<MODE>(g, smem, tile, split, r0, min(B, r0 + rows_per_wg), srt, B, rs, gpart, N);
+    adj_tile_body<MODE, W>(g, smem, tile, split, r0, min(B, r0 + rows_per_wg), srt, B, rs, gpart, N);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1181,6 +1186,49 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Issue-rate probes (roofline denominators).  Every lane runs `iters` rounds of eight
+// independent chains of one instruction kind; with 8 work-groups of 256 threads per compute
+// unit the chains' latencies are hidden and the launch time measures the issue rate.
+//   kind 0: v_fma_f32        kind 1: v_sin_f32        kind 2: v_cos_f32
+//   kind 3: the entry body of the tile kernels: phase FMA, sin, cos and four FMAs per chain step
+// ------------------------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void k_probe_rate(float *__restrict__ out, int iters, float seed) {
+    float x[8], a[8], b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        x[j] = seed + 1e-3f * (float)threadIdx.x + 0.125f * (float)j;
+        a[j] = 0.f;
+        b[j] = 0.f;
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (KIND == 0) {
+                x[j] = fmaf(x[j], 0.9990234375f, 0.0009765625f);
+            } else if (KIND == 1) {
+                x[j] = __builtin_amdgcn_sinf(x[j]);
+            } else if (KIND == 2) {
+                x[j] = __builtin_amdgcn_cosf(x[j]);
+            } else {
+                const float ph = fmaf(x[j], 0.9990234375f, 0.0009765625f);
+                const float sn = __builtin_amdgcn_sinf(ph);
+                const float cs = __builtin_amdgcn_cosf(ph);
+                a[j] = fmaf(cs, 0.5f, a[j]);
+                a[j] = fmaf(sn, 0.25f, a[j]);
+                b[j] = fmaf(cs, 0.25f, b[j]);
+                b[j] = fmaf(-sn, 0.5f, b[j]);
+                x[j] = ph;
+            }
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += x[j] + a[j] + b[j];
+    if (s == 1234.5f) out[blockIdx.x] = s;  // keeps the chains live; never true in practice
+}
+
 #include "spgm_mm.inc"
 #include "spgm_sf.inc"
 #include "spgm_reg.inc"
@@ -1222,6 +1270,11 @@ class DeviceGuard {
 
 }  // namespace
 
+// Launch shape of a tile kernel: row splits (work-groups per brick) and waves per work-group.
+struct TileShape {
+    int splits, waves;
+};
+
 struct spgm_plan {
     int device = 0;
     int phase_mode = 0;
@@ -1261,8 +1314,11 @@ struct spgm_plan {
     bool timing = false;
     std::vector<hipEvent_t> ev_fwd, ev_adj;  // pairs: [2k] start, [2k+1] stop
     size_t n_fwd = 0, n_adj = 0;
-    // autotuned row splits per minibatch size: B -> (forward, adjoint)
-    std::map<int, std::pair<int, int>> tuned;
+    // waves per work-group of the tile kernels when not tuned (8, or 16 where the brick tables
+    // leave room for only one work-group per compute unit)
+    int tile_waves = 8;
+    // autotuned launch shapes per minibatch size: B -> (forward, adjoint)
+    std::map<int, std::pair<TileShape, TileShape>> tuned;
     // shared-geometry batches: packed right-hand sides [tile][z][8][2][64], forward partials
     // [brick run][row][32], packed residuals [row/8][2][64], adjoint partials [split][voxel][32]
     u32x4 *d_mm_s = nullptr;
@@ -1333,14 +1389,26 @@ int default_splits(const spgm_plan *p, int B) {
     return std::min(want, max_splits(B));
 }
 
-int fwd_splits(const spgm_plan *p, int B) {
+TileShape fwd_shape(const spgm_plan *p, int B) {
     const auto it = p->tuned.find(B);
-    return it != p->tuned.end() ? it->second.first : default_splits(p, B);
+    return it != p->tuned.end() ? it->second.first : TileShape{default_splits(p, B), p->tile_waves};
 }
 
-int adj_splits(const spgm_plan *p, int B) {
+TileShape adj_shape(const spgm_plan *p, int B) {
     const auto it = p->tuned.find(B);
-    return it != p->tuned.end() ? it->second.second : default_splits(p, B);
+    return it != p->tuned.end() ? it->second.second : TileShape{default_splits(p, B), p->tile_waves};
+}
+
+int fwd_splits(const spgm_plan *p, int B) { return fwd_shape(p, B).splits; }
+int adj_splits(const spgm_plan *p, int B) { return adj_shape(p, B).splits; }
+
+// LDS bytes of a tile work-group of `waves` waves: antenna terms, staged rows (16 B row data and
+// 8 B row value each), the deferred step's brick iterate, and the L-side table (reused by the
+// adjoint for its per-wave column sums).
+size_t tile_lds(const Geo &g, int waves) {
+    return kAntBytes * (size_t)(g.T + g.R) + (size_t)waves * kWave * (sizeof(float4) + sizeof(float2)) +
+           sizeof(float2) * kBrick +
+           std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * (size_t)waves);
 }
 
 // A captured solve graph holds workspace pointers: drop it whenever the workspace moves.
@@ -1432,65 +1500,95 @@ hipEvent_t *timing_slot(spgm_plan *p, std::vector<hipEvent_t> &pool, size_t &use
     return &pool[2 * used++];
 }
 
-int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, hipStream_t st,
-                         const SStep &up = SStep{}) {
-    const int splits = fwd_splits(p, B);
-    const int rpw = (B + splits - 1) / splits;
-    hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
-    if (ev) hipEventRecord(ev[0], st);
-    const dim3 grid(p->n_tiles, splits);
+// Device workspace of one SPGM step: forward partials [tiles][B], scaled residuals [B] and
+// adjoint partials [splits][N] (the plan's own buffers unless a caller brings others).
+struct StepWork {
+    float2 *part, *rs, *gpart;
+};
+
+StepWork plan_work(const spgm_plan *p) { return StepWork{p->d_part, p->d_rs, p->d_gpart}; }
+
+template <int W>
+void launch_fwd(const spgm_plan *p, dim3 grid, hipStream_t st, const int4 *srt, int B, int rpw, const float2 *s,
+                float2 *part, const SStep &up) {
+    const size_t lds = tile_lds(p->geo, W);
     switch (p->phase_mode) {
     case SPGM_PHASE_F64:
-        k_fwd_tile<SPGM_PHASE_F64><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part, up);
+        k_fwd_tile<SPGM_PHASE_F64, W><<<grid, W * kWave, lds, st>>>(p->geo, srt, B, rpw, s, part, up);
         break;
     case SPGM_PHASE_NAIVE32:
-        k_fwd_tile<SPGM_PHASE_NAIVE32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part, up);
+        k_fwd_tile<SPGM_PHASE_NAIVE32, W><<<grid, W * kWave, lds, st>>>(p->geo, srt, B, rpw, s, part, up);
         break;
     default:
-        k_fwd_tile<SPGM_PHASE_COMP32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, s, p->d_part, up);
+        k_fwd_tile<SPGM_PHASE_COMP32, W><<<grid, W * kWave, lds, st>>>(p->geo, srt, B, rpw, s, part, up);
     }
+}
+
+template <int W>
+void launch_adj(const spgm_plan *p, dim3 grid, hipStream_t st, const int4 *srt, int B, int rpw, const float2 *rs,
+                float2 *gpart) {
+    const size_t lds = tile_lds(p->geo, W);
+    switch (p->phase_mode) {
+    case SPGM_PHASE_F64:
+        k_adj_tile<SPGM_PHASE_F64, W><<<grid, W * kWave, lds, st>>>(p->geo, srt, B, rpw, rs, gpart, (int)p->N);
+        break;
+    case SPGM_PHASE_NAIVE32:
+        k_adj_tile<SPGM_PHASE_NAIVE32, W><<<grid, W * kWave, lds, st>>>(p->geo, srt, B, rpw, rs, gpart, (int)p->N);
+        break;
+    default:
+        k_adj_tile<SPGM_PHASE_COMP32, W><<<grid, W * kWave, lds, st>>>(p->geo, srt, B, rpw, rs, gpart, (int)p->N);
+    }
+}
+
+int run_forward_partials(spgm_plan *p, const int4 *srt, const float2 *s, int B, hipStream_t st,
+                         const SStep &up = SStep{}, float2 *part = nullptr) {
+    if (!part) part = p->d_part;
+    const TileShape sh = fwd_shape(p, B);
+    const int rpw = (B + sh.splits - 1) / sh.splits;
+    hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
+    if (ev) hipEventRecord(ev[0], st);
+    const dim3 grid(p->n_tiles, sh.splits);
+    if (sh.waves == 16)
+        launch_fwd<16>(p, grid, st, srt, B, rpw, s, part, up);
+    else
+        launch_fwd<8>(p, grid, st, srt, B, rpw, s, part, up);
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("forward");
 }
 
-int run_adjoint_partials(spgm_plan *p, const int4 *srt, int B, hipStream_t st) {
-    const int splits = adj_splits(p, B);
-    const int rpw = (B + splits - 1) / splits;
+int run_adjoint_partials(spgm_plan *p, const int4 *srt, int B, hipStream_t st, const float2 *rs = nullptr,
+                         float2 *gpart = nullptr) {
+    if (!rs) rs = p->d_rs;
+    if (!gpart) gpart = p->d_gpart;
+    const TileShape sh = adj_shape(p, B);
+    const int rpw = (B + sh.splits - 1) / sh.splits;
     hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
     if (ev) hipEventRecord(ev[0], st);
-    const dim3 grid(p->n_tiles, splits);
-    switch (p->phase_mode) {
-    case SPGM_PHASE_F64:
-        k_adj_tile<SPGM_PHASE_F64><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs, p->d_gpart,
-                                                                         (int)p->N);
-        break;
-    case SPGM_PHASE_NAIVE32:
-        k_adj_tile<SPGM_PHASE_NAIVE32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs,
-                                                                             p->d_gpart, (int)p->N);
-        break;
-    default:
-        k_adj_tile<SPGM_PHASE_COMP32><<<grid, kThreads, p->lds_bytes, st>>>(p->geo, srt, B, rpw, p->d_rs, p->d_gpart,
-                                                                            (int)p->N);
-    }
+    const dim3 grid(p->n_tiles, sh.splits);
+    if (sh.waves == 16)
+        launch_adj<16>(p, grid, st, srt, B, rpw, rs, gpart);
+    else
+        launch_adj<8>(p, grid, st, srt, B, rpw, rs, gpart);
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("adjoint");
 }
 
 int run_row_reduce(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const float2 *y, float2 *out_user,
-                   float2 *out_scaled, hipStream_t st) {
-    k_row_reduce<<<(B + kRedRows - 1) / kRedRows, kRedRows * kRedGroups, 0, st>>>(p->geo, p->d_part, p->n_tiles, B,
-                                                                                  srt, rows, y, out_user, out_scaled);
+                   float2 *out_scaled, hipStream_t st, const float2 *part = nullptr) {
+    if (!part) part = p->d_part;
+    k_row_reduce<<<(B + kRedRows - 1) / kRedRows, kRedRows * kRedGroups, 0, st>>>(p->geo, part, p->n_tiles, B, srt,
+                                                                                  rows, y, out_user, out_scaled);
     return launch_check("row reduce");
 }
 
-// One SPGM iteration on already sorted rows.
+// One SPGM iteration on already sorted rows, in workspace w.
 int step_sorted(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const float2 *y, float2 *s, float eta,
-                float alpha, hipStream_t st) {
+                float alpha, hipStream_t st, const StepWork &w) {
     int rc;
-    if ((rc = run_forward_partials(p, srt, s, B, st))) return rc;
-    if ((rc = run_row_reduce(p, srt, rows, B, y, nullptr, p->d_rs, st))) return rc;
-    if ((rc = run_adjoint_partials(p, srt, B, st))) return rc;
-    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, nullptr, s,
+    if ((rc = run_forward_partials(p, srt, s, B, st, SStep{}, w.part))) return rc;
+    if ((rc = run_row_reduce(p, srt, rows, B, y, nullptr, w.rs, st, w.part))) return rc;
+    if ((rc = run_adjoint_partials(p, srt, B, st, w.rs, w.gpart))) return rc;
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(w.gpart, adj_splits(p, B), (int)p->N, nullptr, s,
                                                              eta / (float)B, alpha);
     return launch_check("column reduce");
 }
@@ -1555,7 +1653,7 @@ int run_tv_prox(spgm_plan *p, float2 *v, float alpha, int iters, hipStream_t st)
 // One iteration on already sorted rows with the prox of `reg` (validated, workspace allocated).
 int step_sorted_reg(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, const float2 *y, float2 *s, float eta,
                     float alpha, const spgm_regularizer &reg, hipStream_t st) {
-    if (reg.kind == SPGM_REG_L1) return step_sorted(p, srt, rows, B, y, s, eta, alpha, st);
+    if (reg.kind == SPGM_REG_L1) return step_sorted(p, srt, rows, B, y, s, eta, alpha, st, plan_work(p));
     int rc;
     if ((rc = run_forward_partials(p, srt, s, B, st))) return rc;
     if ((rc = run_row_reduce(p, srt, rows, B, y, nullptr, p->d_rs, st))) return rc;
@@ -2029,20 +2127,28 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     g.kappa = p->d_kappa;
     g.q = p->d_q;
     const size_t A = (size_t)(T + R);
-    p->lds_bytes = kAntBytes * A + kSub * (sizeof(float4) + sizeof(float2)) + sizeof(float2) * kBrick +
-                   std::max<size_t>(sizeof(float2) * kBrick * g.nL, sizeof(float2) * kBrick * kWaves);
+    p->lds_bytes = tile_lds(g, kWaves);
     if (p->lds_bytes > (size_t)kMaxLds) {
         spgm_plan_destroy(p);
         return fail(SPGM_E_UNSUPPORTED, "spgm_plan_create: LDS footprint exceeds 160 KiB");
     }
+    // Two work-groups of eight waves per compute unit (four waves per SIMD) where their brick
+    // tables fit twice in LDS; otherwise one work-group of sixteen waves keeps four per SIMD.
+    p->tile_waves = (2 * p->lds_bytes > (size_t)kMaxLds && tile_lds(g, 16) <= (size_t)kMaxLds) ? 16 : 8;
     hipFuncSetAttribute((const void *)k_sort_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)(sizeof(unsigned long long) * kSortChunk));
-    const void *tile_kernels[] = {
-        (const void *)k_fwd_tile<SPGM_PHASE_COMP32>, (const void *)k_fwd_tile<SPGM_PHASE_F64>,
-        (const void *)k_fwd_tile<SPGM_PHASE_NAIVE32>, (const void *)k_adj_tile<SPGM_PHASE_COMP32>,
-        (const void *)k_adj_tile<SPGM_PHASE_F64>, (const void *)k_adj_tile<SPGM_PHASE_NAIVE32>};
-    for (const void *k : tile_kernels)
+    const void *tile_kernels8[] = {
+        (const void *)k_fwd_tile<SPGM_PHASE_COMP32, 8>, (const void *)k_fwd_tile<SPGM_PHASE_F64, 8>,
+        (const void *)k_fwd_tile<SPGM_PHASE_NAIVE32, 8>, (const void *)k_adj_tile<SPGM_PHASE_COMP32, 8>,
+        (const void *)k_adj_tile<SPGM_PHASE_F64, 8>, (const void *)k_adj_tile<SPGM_PHASE_NAIVE32, 8>};
+    for (const void *k : tile_kernels8)
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
+    const void *tile_kernels16[] = {
+        (const void *)k_fwd_tile<SPGM_PHASE_COMP32, 16>, (const void *)k_fwd_tile<SPGM_PHASE_F64, 16>,
+        (const void *)k_fwd_tile<SPGM_PHASE_NAIVE32, 16>, (const void *)k_adj_tile<SPGM_PHASE_COMP32, 16>,
+        (const void *)k_adj_tile<SPGM_PHASE_F64, 16>, (const void *)k_adj_tile<SPGM_PHASE_NAIVE32, 16>};
+    for (const void *k : tile_kernels16)
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     const void *mm_kernels[] = {
         (const void *)k_mm_fwd<SPGM_MM_BF16, 1>, (const void *)k_mm_fwd<SPGM_MM_BF16, 2>,
         (const void *)k_mm_fwd<SPGM_MM_BF16, 3>, (const void *)k_mm_fwd<SPGM_MM_BF16, 4>,
@@ -2149,7 +2255,27 @@ int spgm_step(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, void 
     if ((rc = ensure_workspace(p, B))) return rc;
     hipStream_t st = (hipStream_t)stream;
     if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
-    if ((rc = step_sorted(p, p->d_srt, rows, B, (const float2 *)y, (float2 *)s, eta, alpha, st))) return rc;
+    if ((rc = step_sorted(p, p->d_srt, rows, B, (const float2 *)y, (float2 *)s, eta, alpha, st, plan_work(p))))
+        return rc;
+    return ok();
+}
+
+int spgm_step_grad(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, void *s, float eta, float alpha,
+                   void *g, void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    if (!g) return fail(SPGM_E_INVALID, "spgm_step_grad: g must be non-NULL");
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    if ((rc = run_forward_partials(p, p->d_srt, (const float2 *)s, B, st))) return rc;
+    if ((rc = run_row_reduce(p, p->d_srt, rows, B, (const float2 *)y, nullptr, p->d_rs, st))) return rc;
+    if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
+    k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, (float2 *)g,
+                                                             (float2 *)s, eta / (float)B, alpha);
+    if ((rc = launch_check("column reduce"))) return rc;
     return ok();
 }
 
@@ -2510,50 +2636,86 @@ int spgm_solve_tol(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t B, 
     return ok();
 }
 
+// Backward of one unrolled iteration from the gradient g = A_B^H (A_B s - y_B) at its entering
+// iterate (rows already sorted into p->d_srt): prox VJP, h = A_B^H A_B zbar, sbar = zbar - step h,
+// and the fixed-order sums of the parameter gradients.
+static int vjp_from_gradient(spgm_plan *p, const int32_t *rows, int B, const float2 *s, const float2 *g, float eta,
+                             float tau, const float2 *sbar_next, float2 *sbar, double *eta_bar, double *tau_bar,
+                             hipStream_t st) {
+    int rc;
+    const int N = (int)p->N;
+    float2 *zbar = p->d_vjp + N, *h = p->d_vjp + 2 * (size_t)N;
+    const int nb = (N + kVjpThreads - 1) / kVjpThreads;
+    const float step = eta / (float)B;
+    k_prox_vjp<<<nb, kVjpThreads, 0, st>>>(s, g, sbar_next, N, step, tau, 1.0f / (float)B, zbar, p->d_vjp_part);
+    if ((rc = launch_check("prox vjp"))) return rc;
+    if ((rc = run_forward_partials(p, p->d_srt, zbar, B, st))) return rc;
+    if ((rc = run_row_reduce(p, p->d_srt, rows, B, nullptr, nullptr, p->d_rs, st))) return rc;
+    if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
+    k_col_reduce<<<(N + 255) / 256, 256, 0, st>>>(p->d_gpart, adj_splits(p, B), N, h, nullptr, 0.f, 0.f);
+    if ((rc = launch_check("column reduce"))) return rc;
+    k_axpy_out<<<(N + 255) / 256, 256, 0, st>>>(zbar, h, N, step, sbar);
+    if ((rc = launch_check("axpy"))) return rc;
+    k_sum_partials<<<1, 256, 0, st>>>(p->d_vjp_part, nb, eta_bar, tau_bar);
+    return launch_check("sum partials");
+}
+
+static int vjp_check(spgm_plan *p, const int32_t *rows, int B, const void *s, const void *other, float eta, float tau,
+                     const void *sbar_next, const void *sbar, const double *eta_bar, const double *tau_bar,
+                     const char *who) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if (!other || !s || !sbar_next || !sbar || !eta_bar || !tau_bar)
+        return fail(SPGM_E_INVALID, "%s: NULL pointer argument", who);
+    if (!(std::isfinite(eta) && eta > 0) || !(std::isfinite(tau) && tau >= 0))
+        return fail(SPGM_E_INVALID, "%s: eta must be > 0 and tau >= 0, finite", who);
+    return SPGM_OK;
+}
+
 int spgm_unrolled_vjp_step(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, const void *s,
                            float eta, float tau, const void *sbar_next, void *sbar, double *eta_bar,
                            double *tau_bar, void *stream) {
     int rc;
-    if ((rc = check_common(p, rows, B))) return rc;
-    if (!y || !s || !sbar_next || !sbar || !eta_bar || !tau_bar)
-        return fail(SPGM_E_INVALID, "spgm_unrolled_vjp_step: NULL pointer argument");
-    if (!(std::isfinite(eta) && eta > 0) || !(std::isfinite(tau) && tau >= 0))
-        return fail(SPGM_E_INVALID, "spgm_unrolled_vjp_step: eta must be > 0 and tau >= 0, finite");
+    if ((rc = vjp_check(p, rows, B, s, y, eta, tau, sbar_next, sbar, eta_bar, tau_bar, "spgm_unrolled_vjp_step")))
+        return rc;
     DeviceGuard guard(p->device);
     if ((rc = ensure_workspace(p, B)) || (rc = ensure_vjp(p))) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int N = (int)p->N;
-    float2 *g = p->d_vjp, *zbar = p->d_vjp + N, *h = p->d_vjp + 2 * (size_t)N;
-    const int splits = adj_splits(p, B);
-    const int nb = (N + kVjpThreads - 1) / kVjpThreads;
-    const float step = eta / (float)B;
+    float2 *g = p->d_vjp;
     // recompute g = A_B^H (A_B s - y_B) at the iterate entering the iteration
     if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
     if ((rc = run_forward_partials(p, p->d_srt, (const float2 *)s, B, st))) return rc;
     if ((rc = run_row_reduce(p, p->d_srt, rows, B, (const float2 *)y, nullptr, p->d_rs, st))) return rc;
     if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
-    k_col_reduce<<<(N + 255) / 256, 256, 0, st>>>(p->d_gpart, splits, N, g, nullptr, 0.f, 0.f);
+    k_col_reduce<<<(N + 255) / 256, 256, 0, st>>>(p->d_gpart, adj_splits(p, B), N, g, nullptr, 0.f, 0.f);
     if ((rc = launch_check("column reduce"))) return rc;
-    // prox VJP and parameter-gradient partials
-    k_prox_vjp<<<nb, kVjpThreads, 0, st>>>((const float2 *)s, g, (const float2 *)sbar_next, N, step, tau,
-                                           1.0f / (float)B, zbar, p->d_vjp_part);
-    if ((rc = launch_check("prox vjp"))) return rc;
-    // h = A_B^H A_B zbar
-    if ((rc = run_forward_partials(p, p->d_srt, zbar, B, st))) return rc;
-    if ((rc = run_row_reduce(p, p->d_srt, rows, B, nullptr, nullptr, p->d_rs, st))) return rc;
-    if ((rc = run_adjoint_partials(p, p->d_srt, B, st))) return rc;
-    k_col_reduce<<<(N + 255) / 256, 256, 0, st>>>(p->d_gpart, splits, N, h, nullptr, 0.f, 0.f);
-    if ((rc = launch_check("column reduce"))) return rc;
-    k_axpy_out<<<(N + 255) / 256, 256, 0, st>>>(zbar, h, N, step, (float2 *)sbar);
-    if ((rc = launch_check("axpy"))) return rc;
-    k_sum_partials<<<1, 256, 0, st>>>(p->d_vjp_part, nb, eta_bar, tau_bar);
-    if ((rc = launch_check("sum partials"))) return rc;
+    if ((rc = vjp_from_gradient(p, rows, B, (const float2 *)s, g, eta, tau, (const float2 *)sbar_next, (float2 *)sbar,
+                                eta_bar, tau_bar, st)))
+        return rc;
+    return ok();
+}
+
+int spgm_unrolled_vjp_step_g(spgm_plan *p, const int32_t *rows, int32_t B, const void *s, const void *g, float eta,
+                             float tau, const void *sbar_next, void *sbar, double *eta_bar, double *tau_bar,
+                             void *stream) {
+    int rc;
+    if ((rc = vjp_check(p, rows, B, s, g, eta, tau, sbar_next, sbar, eta_bar, tau_bar, "spgm_unrolled_vjp_step_g")))
+        return rc;
+    DeviceGuard guard(p->device);
+    if ((rc = ensure_workspace(p, B)) || (rc = ensure_vjp(p))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = run_sort(p, rows, B, 1, p->d_srt, st))) return rc;
+    if ((rc = vjp_from_gradient(p, rows, B, (const float2 *)s, (const float2 *)g, eta, tau, (const float2 *)sbar_next,
+                                (float2 *)sbar, eta_bar, tau_bar, st)))
+        return rc;
     return ok();
 }
 
 // ------------------------------------------------------------------------------------------
-// Autotuner: time the two tile kernels over candidate row splits (minibatch rows per
-// work-group) and keep the fastest per kernel; results are cached in a small JSON file.
+// Autotuner: time the two tile kernels over candidate launch shapes (row splits, i.e. minibatch
+// rows per work-group, and 8 or 16 waves per work-group) and keep the fastest per kernel;
+// results are cached in a small JSON file.
 // ------------------------------------------------------------------------------------------
 static std::string tune_key(const spgm_plan *p, int B) {
     hipDeviceProp_t prop;
@@ -2567,7 +2729,8 @@ static std::string tune_key(const spgm_plan *p, int B) {
     return k.str();
 }
 
-// The cache is a flat JSON object {"key": [fwd_splits, adj_splits, fwd_ms, adj_ms], ...}.
+// The cache is a flat JSON object {"key": [fwd_splits, adj_splits, fwd_ms, adj_ms, fwd_waves,
+// adj_waves], ...}; entries without the last two use the plan's default waves per work-group.
 static std::map<std::string, std::vector<double>> read_cache(const std::string &path) {
     std::map<std::string, std::vector<double>> out;
     std::ifstream f(path);
@@ -2620,9 +2783,12 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
     std::map<std::string, std::vector<double>> cache;
     if (!path.empty()) cache = read_cache(path);
     const auto hit = cache.find(key);
+    auto waves_ok = [p](int w) { return w == 8 || (w == 16 && tile_lds(p->geo, 16) <= (size_t)kMaxLds); };
     if (hit != cache.end() && hit->second.size() >= 2) {
-        p->tuned[B] = {std::max(1, std::min((int)hit->second[0], max_splits(B))),
-                       std::max(1, std::min((int)hit->second[1], max_splits(B)))};
+        const int fw = hit->second.size() >= 6 ? (int)hit->second[4] : p->tile_waves;
+        const int aw = hit->second.size() >= 6 ? (int)hit->second[5] : p->tile_waves;
+        p->tuned[B] = {TileShape{std::max(1, std::min((int)hit->second[0], max_splits(B))), waves_ok(fw) ? fw : 8},
+                       TileShape{std::max(1, std::min((int)hit->second[1], max_splits(B))), waves_ok(aw) ? aw : 8}};
     } else {
         // candidates: 1, 2, 3, 4, 6, 8, 12, 16, ... rows per work-group >= 64
         std::vector<int> cand;
@@ -2660,16 +2826,20 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
             rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune: copy failed");
         // size the workspace for the largest candidate
         if (!rc) {
-            p->tuned[B] = {max_c, max_c};
+            p->tuned[B] = {TileShape{max_c, 8}, TileShape{max_c, 8}};
             rc = ensure_workspace(p, B);
         }
         if (!rc) rc = run_sort(p, drows, B, 1, p->d_srt, st);
         double best_f = 1e30, best_a = 1e30;
-        int bf = 1, ba = 1;
+        TileShape bf{1, 8}, ba{1, 8};
         const bool timing = p->timing;
         p->timing = false;
-        for (size_t ci = 0; !rc && ci < cand.size(); ++ci) {
-            p->tuned[B] = {cand[ci], cand[ci]};
+        std::vector<TileShape> shapes;
+        for (int w : {8, 16})
+            if (waves_ok(w))
+                for (int c : cand) shapes.push_back(TileShape{c, w});
+        for (size_t ci = 0; !rc && ci < shapes.size(); ++ci) {
+            p->tuned[B] = {shapes[ci], shapes[ci]};
             for (int which = 0; which < 2 && !rc; ++which) {
                 float best = 1e30f;
                 for (int rep = 0; rep < 4 && !rc; ++rep) {
@@ -2686,11 +2856,11 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
                 }
                 if (which == 0 && best < best_f) {
                     best_f = best;
-                    bf = cand[ci];
+                    bf = shapes[ci];
                 }
                 if (which == 1 && best < best_a) {
                     best_a = best;
-                    ba = cand[ci];
+                    ba = shapes[ci];
                 }
             }
         }
@@ -2706,15 +2876,15 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
         }
         p->tuned[B] = {bf, ba};
         if (!path.empty()) {
-            cache[key] = {(double)bf, (double)ba, best_f, best_a};
+            cache[key] = {(double)bf.splits, (double)ba.splits, best_f, best_a, (double)bf.waves, (double)ba.waves};
             write_cache(path, cache);
         }
     }
     int rc;
     if ((rc = ensure_workspace(p, B))) return rc;
     drop_graph(p);  // launch shapes changed
-    if (fwd_out) *fwd_out = p->tuned[B].first;
-    if (adj_out) *adj_out = p->tuned[B].second;
+    if (fwd_out) *fwd_out = p->tuned[B].first.splits;
+    if (adj_out) *adj_out = p->tuned[B].second.splits;
     return ok();
 }
 
@@ -2935,6 +3105,60 @@ int spgm_batch_solve(spgm_batch *b, int32_t iters, const int32_t *B, const int32
     hipGraphExecDestroy(ex);  // safe: destruction is deferred until the launch completes
     hipGraphDestroy(g);
     if (le != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_batch_solve: graph launch failed");
+    return ok();
+}
+
+int spgm_calibrate(int32_t kind, int32_t iters, double *ops_per_s, double *ms) {
+    if (kind < 0 || kind > 3) return fail(SPGM_E_INVALID, "spgm_calibrate: kind must be 0..3");
+    if (iters < 1 || iters > (1 << 20)) return fail(SPGM_E_INVALID, "spgm_calibrate: iters must be in [1, 2^20]");
+    if (!ops_per_s) return fail(SPGM_E_INVALID, "spgm_calibrate: ops_per_s is NULL");
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(SPGM_E_DEVICE, "spgm_calibrate: no HIP device");
+    const int grid = prop.multiProcessorCount * 8;
+    float *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(&out, sizeof(float) * grid) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        hipFree(out);
+        if (e0) hipEventDestroy(e0);
+        return fail(SPGM_E_NOMEM, "spgm_calibrate: allocation failed");
+    }
+    auto launch = [&](int n) {
+        switch (kind) {
+        case 0: k_probe_rate<0><<<grid, 256>>>(out, n, 0.5f); break;
+        case 1: k_probe_rate<1><<<grid, 256>>>(out, n, 0.5f); break;
+        case 2: k_probe_rate<2><<<grid, 256>>>(out, n, 0.5f); break;
+        default: k_probe_rate<3><<<grid, 256>>>(out, n, 0.5f);
+        }
+    };
+    launch(iters);  // warm-up
+    hipEventRecord(e0, nullptr);
+    launch(iters);
+    hipEventRecord(e1, nullptr);
+    float t = 0.f;
+    const bool good = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess &&
+                      hipGetLastError() == hipSuccess;
+    hipFree(out);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!good || t <= 0.f) return fail(SPGM_E_DEVICE, "spgm_calibrate: timing failed");
+    // chain steps per lane: 8 chains x iters (kind 3: one entry body per chain step)
+    *ops_per_s = (double)grid * 256.0 * 8.0 * (double)iters / (1e-3 * (double)t);
+    if (ms) *ms = (double)t;
+    return ok();
+}
+
+int spgm_plan_launch_shape(const spgm_plan *p, int32_t B, int32_t *fwd_splits, int32_t *fwd_waves,
+                           int32_t *adj_splits, int32_t *adj_waves) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm_plan_launch_shape: plan is NULL");
+    if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm_plan_launch_shape: B=%d outside [1, %d]", B, kMaxB);
+    const TileShape f = fwd_shape(p, B), a = adj_shape(p, B);
+    if (fwd_splits) *fwd_splits = f.splits;
+    if (fwd_waves) *fwd_waves = f.waves;
+    if (adj_splits) *adj_splits = a.splits;
+    if (adj_waves) *adj_waves = a.waves;
     return ok();
 }
 

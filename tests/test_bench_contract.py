@@ -22,17 +22,18 @@ def test_several_gpus_are_refused_with_a_message():
 def test_traffic_record_needs_matching_source_and_split(tmp_path, monkeypatch):
     sha = bench.source_sha()
     data = {
-        "k_fwd_tile/c1/splits4": {"source_sha": sha, "bytes_per_launch": 123},
-        "k_fwd_tile/c1/splits2": {"source_sha": "0" * 16, "bytes_per_launch": 456},
+        "k_fwd_tile/c1/splits4/waves8": {"source_sha": sha, "bytes_per_launch": 123},
+        "k_fwd_tile/c1/splits2/waves8": {"source_sha": "0" * 16, "bytes_per_launch": 456},
         "k_row_reduce/c1": {"source_sha": sha, "bytes_per_launch": 789},
     }
     path = tmp_path / "traffic.json"
     path.write_text(json.dumps(data))
     monkeypatch.setattr(bench, "TRAFFIC", str(path))
-    assert bench.stored_traffic("k_fwd_tile", "c1", 4) == 123
-    assert bench.stored_traffic("k_fwd_tile", "c1", 2) is None  # measured on other sources
-    assert bench.stored_traffic("k_fwd_tile", "c1", 9) is None  # split never measured
-    assert bench.stored_traffic("k_fwd_tile", "c1") is None     # tile kernels are keyed by split
+    assert bench.stored_traffic("k_fwd_tile", "c1", (4, 8)) == 123
+    assert bench.stored_traffic("k_fwd_tile", "c1", (2, 8)) is None   # measured on other sources
+    assert bench.stored_traffic("k_fwd_tile", "c1", (9, 8)) is None   # split never measured
+    assert bench.stored_traffic("k_fwd_tile", "c1", (4, 16)) is None  # other waves per work-group
+    assert bench.stored_traffic("k_fwd_tile", "c1") is None     # tile kernels are keyed by launch shape
     assert bench.stored_traffic("k_row_reduce", "c1") == 789
     monkeypatch.setattr(bench, "TRAFFIC", str(tmp_path / "missing.json"))
     assert bench.stored_traffic("k_row_reduce", "c1") is None
@@ -43,7 +44,8 @@ def test_committed_traffic_records_name_their_split_and_source():
     for key, rec in data.items():
         kernel = key.split("/")[0]
         if kernel in ("k_fwd_tile", "k_adj_tile"):
-            assert key.rsplit("/", 1)[1].startswith("splits"), key
+            parts = key.split("/")
+            assert parts[2].startswith("splits") and parts[3].startswith("waves"), key
         assert len(rec["source_sha"]) == 16
         # read + write, each rounded down separately
         assert abs(rec["bytes_per_launch"] - rec["read_bytes"] - rec["write_bytes"]) <= 1

@@ -150,3 +150,42 @@ def test_unrolled_gradient_step_reduces_loss(bd):
         l1 = loss_of(-step * ga, -step * gb)
     say("loss %.6e -> %.6e after one normalised gradient step" % (float(l0), float(l1)))
     assert float(l1) < float(l0)
+
+
+def test_backward_from_kept_gradient_is_bitwise_the_recomputing_one(bd):
+    """spgm_step_grad returns the iterate of spgm_step and the gradient A_B^H (A_B s - y_B) at the
+    entering iterate; the backward step given that gradient (two entry passes) equals the one
+    that recomputes it from y (four entry passes) bit for bit, and the gradient matches the
+    oracle's (Eq. 6 without the 1/B)."""
+    geom = W.config_geometry("c4")
+    orc = Oracle(geom)
+    plan = bd.Plan(geom)
+    rows = W.draw_rows(orc.M, 2048, 1, seed=61)[0]
+    y = W.random_complex(orc.M, seed=62).astype(np.complex64)
+    s0 = (0.1 * W.random_complex(orc.N, seed=63)).astype(np.complex64)
+    sbar_next = W.random_complex(orc.N, seed=64).astype(np.complex64)
+    eta, tau = 8e-3, 2e-3
+    r_d, y_d = idev(rows), cdev(y)
+    a, b = cdev(s0), cdev(s0)
+    g = torch.empty_like(a)
+    plan.spgm_step_grad(r_d, y_d, a, eta, tau, g)
+    plan.spgm_step(r_d, y_d, b, eta, tau)
+    assert torch.equal(a, b)
+    g_ref = orc.adjoint(rows, orc.forward(rows, s0.astype(np.complex128)) - y.astype(np.complex128)[rows])
+    e_g = rel_l2(host(g), g_ref)
+    outs = []
+    for use_g in (True, False):
+        sb = cdev(sbar_next)
+        eb = torch.zeros(1, dtype=torch.float64, device="cuda")
+        tb = torch.zeros(1, dtype=torch.float64, device="cuda")
+        if use_g:
+            plan.spgm_unrolled_vjp_step_g(r_d, cdev(s0), g, eta, tau, sb, sb, eb, tb)
+        else:
+            plan.spgm_unrolled_vjp_step(r_d, y_d, cdev(s0), eta, tau, sb, sb, eb, tb)
+        torch.cuda.synchronize()
+        outs.append((sb.cpu().numpy(), float(eb.item()), float(tb.item())))
+    plan.close()
+    say("step_grad: gradient rel_l2 %.3e vs oracle; kept-gradient backward bitwise equal: %s" % (
+        e_g, np.array_equal(outs[0][0], outs[1][0])))
+    assert e_g <= 1e-5
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]

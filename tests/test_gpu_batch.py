@@ -113,7 +113,13 @@ def test_persistent_work_groups_walk_many_items(bd):
     assert n_items >= 3 * wg
     assert max(-(-r.shape[1] // rps) for r in rows) >= 4
     etas = [2e-3 * (1 + 0.1 * i) for i in range(len(geoms))]
-    alphas = [2e-4] * len(geoms)
+    # thresholds at the median magnitude of each scene's first gradient step (oracle), so that
+    # the prox zeroes about half of the voxels
+    alphas = []
+    for i, geom in enumerate(geoms):
+        s64 = s0[i].astype(np.complex128)
+        v = s64 - etas[i] * Oracle(geom).gradient(rows[i][0], ys[i].astype(np.complex128), s64)
+        alphas.append(float(np.float32(np.median(np.abs(v)))))
     batch = bd.Batch(geoms)
     out = {}
     for max_wg in (wg, 0):
