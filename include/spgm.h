@@ -127,6 +127,19 @@ int spgm_step(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d
 int spgm_step_grad(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d, void *s_d,
                    float eta, float alpha, void *g_d, void *stream);
 
+/* spgm_step for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and launch shapes as
+ * spgm_step, so the same result bit for bit, with the step's workspace (sorted rows, forward
+ * partials, scaled residuals, adjoint partials) carved from a fixed 64 MiB device array that the
+ * library holds on every GPU it runs on until the process ends; the call itself allocates
+ * nothing.  The plan (created beforehand) supplies the geometry.  Workspace needed:
+ * 16 B + 8 B x (voxel bricks + 1) per row plus 8 B x N x (adjoint row splits), each rounded up to
+ * 256 B; above 64 MiB the call fails with SPGM_E_UNSUPPORTED (about B = 15 000 rows on a
+ * 64 x 64 x 32 grid, 1 800 on a 128 x 128 x 64 grid; spgm_step has no such limit).  Every call on one GPU uses that GPU's one
+ * array: calls that overlap on one GPU (other streams, other threads, other plans) race and must
+ * be serialised by the caller.  Arguments and errors as spgm_step. */
+int spgm_step_noalloc(spgm_plan *plan, const int32_t *rows_d, int32_t B, const void *y_d, void *s_d,
+                      float eta, float alpha, void *stream);
 
 /* `iters` SPGM iterations; iteration k uses rows_d[k*B .. k*B + B - 1] (rows_d: int32[iters*B]).
  * Bitwise equal to `iters` calls of spgm_step.  iters >= 0.  Intermediate iterates alternate

@@ -41,7 +41,7 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_forward_batched", "spgm_adjoint_batched", "spgm_step_batched", "spgm_solve_batched",
             "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured",
             "spgm_prox", "spgm_step_reg", "spgm_solve_reg", "spgm_phase_window",
-            "spgm_solve_tol", "spgm_batch_options", "spgm_step_grad",
+            "spgm_solve_tol", "spgm_batch_options", "spgm_step_noalloc", "spgm_step_grad",
             "spgm_unrolled_vjp_step_g", "spgm_plan_launch_shape", "spgm_calibrate")
 
 _dp = C.POINTER(C.c_double)
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "spgm_solve_reg": [vp, C.POINTER(SpgmRegularizer), vp, i32, i32, vp, vp, f32, f32, vp],
         "spgm_phase_window": [C.POINTER(SpgmGeometry), C.POINTER(C.c_double)],
         "spgm_batch_options": [vp, i32, i32],
+        "spgm_step_noalloc": [vp, vp, i32, vp, vp, f32, f32, vp],
         "spgm_step_grad": [vp, vp, i32, vp, vp, f32, f32, vp, vp],
         "spgm_plan_launch_shape": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
         "spgm_calibrate": [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
@@ -265,6 +266,16 @@ class Plan:
         _check(self._lib.spgm_step(self._h, _dev(rows, torch.int32, "rows"), B,
                                    _dev(y, torch.complex64, "y", self.M), _dev(s, torch.complex64, "s", self.N),
                                    float(eta), float(alpha), _stream_ptr(stream)))
+        return s
+
+    def spgm_step_noalloc(self, rows, y, s, eta, alpha, stream=None):
+        """spgm_step in the library's fixed scratch array (no device allocation in the call)."""
+        import torch
+        B = rows.numel()
+        _check(self._lib.spgm_step_noalloc(self._h, _dev(rows, torch.int32, "rows"), B,
+                                           _dev(y, torch.complex64, "y", self.M),
+                                           _dev(s, torch.complex64, "s", self.N), float(eta), float(alpha),
+                                           _stream_ptr(stream)))
         return s
 
     def spgm_solve(self, rows_table, y, s, eta, alpha, stream=None):

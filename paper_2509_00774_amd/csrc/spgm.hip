@@ -43,11 +43,18 @@
 #include <cstdlib>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
 
 #include "spgm.h"
+
+// Workspace of spgm_step_noalloc: a fixed device array, one copy on every GPU the library runs
+// on, held until the process ends.  Host code never passes this name to a kernel (on the host
+// it is only a stand-in for the symbol); it uses the device address resolved per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
@@ -1268,6 +1275,26 @@ class DeviceGuard {
     int prev_ = -1, dev_ = 0;
 };
 
+// Device address of `scratch` on device `dev` (current), resolved once per device: each GPU
+// holds its own copy of the array at its own address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+
+char *scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_addr[dev] = static_cast<char *>(ptr);
+    }
+    return g_scratch_addr[dev];
+}
+
 }  // namespace
 
 // Launch shape of a tile kernel: row splits (work-groups per brick) and waves per work-group.
@@ -1279,6 +1306,7 @@ struct spgm_plan {
     int device = 0;
     int phase_mode = 0;
     int64_t M = 0, N = 0;
+    char *scratch = nullptr;  // device address of `scratch` on this plan's device (or nullptr)
     Geo geo{};
     int n_tiles = 0;
     double *d_ant = nullptr;
@@ -2071,6 +2099,7 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     if (hipGetDevice(&dev) != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_create: no HIP device");
     spgm_plan *p = new spgm_plan();
     p->device = dev;
+    p->scratch = scratch_address(dev);  // set-up of spgm_step_noalloc for this device
     p->phase_mode = phase_mode;
     p->M = M;
     p->N = N;
@@ -2276,6 +2305,41 @@ int spgm_step_grad(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, 
     k_col_reduce<<<(int)((p->N + 255) / 256), 256, 0, st>>>(p->d_gpart, adj_splits(p, B), (int)p->N, (float2 *)g,
                                                              (float2 *)s, eta / (float)B, alpha);
     if ((rc = launch_check("column reduce"))) return rc;
+    return ok();
+}
+
+int spgm_step_noalloc(spgm_plan *p, const int32_t *rows, int32_t B, const void *y, void *s, float eta, float alpha,
+                      void *stream) {
+    int rc;
+    if ((rc = check_common(p, rows, B))) return rc;
+    if ((rc = check_step_args(y, s, eta, alpha))) return rc;
+    if (!p->scratch)
+        return fail(SPGM_E_DEVICE, "spgm_step_noalloc: the scratch array has no device address on device %d",
+                    p->device);
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t b_srt = al(sizeof(int4) * (size_t)B);
+    const size_t b_part = al(sizeof(float2) * (size_t)p->n_tiles * B);
+    const size_t b_rs = al(sizeof(float2) * (size_t)B);
+    const size_t b_gpart = al(sizeof(float2) * (size_t)adj_splits(p, B) * p->N);
+    const size_t need = b_srt + b_part + b_rs + b_gpart;
+    if (need > kScratchBytes)
+        return fail(SPGM_E_UNSUPPORTED,
+                    "spgm_step_noalloc: B=%d on %d voxel bricks needs %zu bytes of workspace, more than the %zu-byte "
+                    "scratch array (use spgm_step)", B, p->n_tiles, need, kScratchBytes);
+    DeviceGuard guard(p->device);
+    char *base = p->scratch;
+    int4 *srt = reinterpret_cast<int4 *>(base);
+    const StepWork w{reinterpret_cast<float2 *>(base + b_srt), reinterpret_cast<float2 *>(base + b_srt + b_part),
+                     reinterpret_cast<float2 *>(base + b_srt + b_part + b_rs)};
+    // Every word of the workspace that a kernel reads is written earlier in this call, so the
+    // previous call's contents need no clearing.  Timing events are not created here.
+    const bool timing = p->timing;
+    p->timing = false;
+    hipStream_t st = (hipStream_t)stream;
+    rc = run_sort(p, rows, B, 1, srt, st);
+    if (!rc) rc = step_sorted(p, srt, rows, B, (const float2 *)y, (float2 *)s, eta, alpha, st, w);
+    p->timing = timing;
+    if (rc) return rc;
     return ok();
 }
 
