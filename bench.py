@@ -37,11 +37,16 @@ import numpy as np  # noqa: E402
 
 from paper_2509_00774_amd import workloads as W  # noqa: E402
 
-# Issue-slot ceiling of the VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-slots/s.
-# One entry of A applied to a vector needs at least 9 slots: the phase FMA, sin and cos (each at
-# half the FMA rate on gfx950, i.e. 2 slots apiece) and the 4 FMAs of the complex multiply-add.
-VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-SLOTS_PER_ENTRY = 9
+# VALU ceiling in FP32 FMA slots: the chip's 157.3 TFLOP/s FP32 vector peak is 78.64e12 lane-FMAs/s,
+# 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz (measured on gfx950: plain v_fma_f32 issue at 25-32 lanes per
+# SIMD and clock, `--workload calib`).  Transcendentals (v_sin_f32, v_cos_f32) issue at a quarter of
+# that rate (measured 8 lanes per SIMD and clock), i.e. 4 slots each.  One entry of A applied to a
+# vector needs at least 13 slots: the phase FMA (1), sin and cos (4 + 4) and the 4 FMAs of the complex
+# multiply-add.
+VALU_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
+TRANS_SLOTS = 4
+SLOTS_PER_ENTRY = 5 + 2 * TRANS_SLOTS
+SLOT_UNIT = "T FP32 lane-slots/s (FMA = 1, sin/cos = 4)"
 STEP_SIZES = os.path.join(ROOT, "tests", "golden", "step_sizes.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 SOURCES = [os.path.join(ROOT, "paper_2509_00774_amd", "csrc", name)
@@ -112,7 +117,13 @@ def timed_solve(args, torch, plan, timed_rows, y, s, eta, alpha):
     return t1 - t0, fwd_ms, fwd_n, adj_ms, adj_n
 
 
-def alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, phase):
+def entry_ceiling(binding):
+    """Measured entry-body rate of the chip (the algorithmic minimum instruction sequence per entry,
+    latency hidden), best of three probe launches; entries/s."""
+    return max(binding.calibrate(3, 4096)[0] for _ in range(3))
+
+
+def alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, phase, ceiling=None):
     """Roofline record of the slower tile kernel: VALU issue slots per launch (entries x the
     9-slot minimum per entry) over its average HIP-event duration, against the issue ceiling.
     shapes: ((forward splits, waves), (adjoint splits, waves)) of the timed launches."""
@@ -124,12 +135,14 @@ def alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, phase):
     kshape = shapes[0 if kname == "k_fwd_tile" else 1]
     traffic = stored_traffic(kname, wl, kshape) if phase == "comp32" else None
     return {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
-            "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+            "unit": SLOT_UNIT, "frac": round(achieved / peak, 4), "traffic": traffic,
             "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
             "avg_launch_ms": round(kavg * 1e3, 5),
             "fwd_tile_ms": round(fwd_avg * 1e3, 5), "adj_tile_ms": round(adj_avg * 1e3, 5),
             "fwd_gentries_per_s": round(entries / fwd_avg / 1e9, 1),
-            "adj_gentries_per_s": round(entries / adj_avg / 1e9, 1)}
+            "adj_gentries_per_s": round(entries / adj_avg / 1e9, 1),
+            "measured_entry_ceiling_gentries_per_s": None if ceiling is None else round(ceiling / 1e9, 1),
+            "frac_of_measured_ceiling": None if ceiling is None else round(entries / kavg / ceiling, 4)}
 
 
 PHASE_DESC = {"comp32": "compensated fp32 (fp64 per-tile reference)", "f64": "fp64 distance and phase",
@@ -197,7 +210,7 @@ def bench_large(args, torch, binding, dev):
         K, dt, 1e3 * dt / K, fwd_ms / max(fwd_n, 1), fwd_n, adj_ms / max(adj_n, 1), adj_n))
     entries = float(B) * N
     shapes = plan.spgm_plan_launch_shape(B)
-    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, args.phase)
+    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, args.phase, entry_ceiling(binding))
 
     cpu = None
     par = {}
@@ -365,7 +378,7 @@ def main():
     entries = float(B) * N
     value = entries * K / dt / 1e9
     shapes = plan.spgm_plan_launch_shape(B)
-    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, args.phase)
+    roofline = alu_roofline(entries, fwd_ms, fwd_n, adj_ms, adj_n, shapes, wl, args.phase, entry_ceiling(binding))
 
     cpu = None
     rel_vs_oracle = None
@@ -506,7 +519,7 @@ def bench_unrolled(args, torch, binding, dev):
         "rel_l2_vs_oracle": None if not par else float("%.3e" % max(par.values())),
         "parity": {k: float("%.3e" % v) for k, v in par.items()},
         "roofline": {"bound": "alu", "kernel": "whole forward + backward", "achieved": round(achieved, 3),
-                     "peak": round(peak, 3), "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4),
+                     "peak": round(peak, 3), "unit": SLOT_UNIT, "frac": round(achieved / peak, 4),
                      "traffic": None, "entries_per_pass": int(entries), "slots_per_entry": SLOTS_PER_ENTRY},
         "cpu_baseline": cpu,
     }
@@ -528,10 +541,11 @@ def bench_calibrate(args, binding):
            "unit": "T entry bodies/s", "n_gpus": 1, "steps": 5, "warmup": 1, "higher_is_better": True,
            "config": {"workload": "calib: 8 work-groups of 256 threads per compute unit, 8 independent chains per lane"},
            "rates_T_per_s": {k: round(v / 1e12, 3) for k, v in rates.items()},
-           "issue_ceiling_T_slots_per_s": round(VALU_SLOTS_PER_S / 1e12, 3),
-           "fma_fraction_of_ceiling": round(fma / VALU_SLOTS_PER_S, 4),
-           "sin_slots": round(fma / rates["sin"], 3), "cos_slots": round(fma / rates["cos"], 3),
-           "entry_body_slots": round(fma / rates["entry_body"], 3)}
+           "fma_peak_T_per_s": round(VALU_SLOTS_PER_S / 1e12, 3),
+           "fma_fraction_of_peak": round(fma / VALU_SLOTS_PER_S, 4),
+           "sin_fraction_of_quarter_rate": round(rates["sin"] * TRANS_SLOTS / VALU_SLOTS_PER_S, 4),
+           "cos_fraction_of_quarter_rate": round(rates["cos"] * TRANS_SLOTS / VALU_SLOTS_PER_S, 4),
+           "entry_body_fraction_of_peak": round(rates["entry_body"] * SLOTS_PER_ENTRY / VALU_SLOTS_PER_S, 4)}
     print(json.dumps(out), flush=True)
 
 
@@ -634,7 +648,7 @@ def bench_ragged(args, torch, binding, dev):
         "rel_l2_vs_oracle_iter2_small_scenes": {str(i): float("%.3e" % e) for i, e in errs2.items()},
         "nmse_db_vs_truth_after_steps_per_scene": {str(i): round(v, 2) for i, v in enumerate(nmse_db)},
         "roofline": {"bound": "alu", "kernel": "whole iteration (both tile phases)", "achieved": round(achieved, 3),
-                     "peak": round(peak, 3), "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4),
+                     "peak": round(peak, 3), "unit": SLOT_UNIT, "frac": round(achieved / peak, 4),
                      "traffic": None, "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY},
         "cpu_baseline": cpu,
     }
@@ -644,9 +658,9 @@ def bench_ragged(args, torch, binding, dev):
 
 # Dense bfloat16 MFMA peak of MI355X (matrix cores, no sparsity).
 MFMA_BF16_PEAK = 2.5e15
-# VALU slots per entry in the batched kernels: phase FMA, sin and cos (2 slots each), the two
+# VALU slots per entry in the batched kernels: phase FMA, sin and cos (4 slots each), the two
 # amplitude multiplies and one packed conversion to 16 bits; the products move to the MFMA.
-MM_SLOTS_PER_ENTRY = 8
+MM_SLOTS_PER_ENTRY = 1 + 2 * TRANS_SLOTS + 3
 
 
 def bench_batched(args, torch, binding, dev):
@@ -760,7 +774,7 @@ def bench_batched(args, torch, binding, dev):
                      "fwd_gentries_per_s": round(entries / fwd_avg / 1e9, 1),
                      "adj_gentries_per_s": round(entries / adj_avg / 1e9, 1),
                      "alu_view": {"achieved": round(entries * MM_SLOTS_PER_ENTRY / kavg / 1e12, 3),
-                                  "peak": round(VALU_SLOTS_PER_S / 1e12, 3), "unit": "T VALU lane-slots/s",
+                                  "peak": round(VALU_SLOTS_PER_S / 1e12, 3), "unit": SLOT_UNIT,
                                   "frac": round(entries * MM_SLOTS_PER_ENTRY / kavg / VALU_SLOTS_PER_S, 4),
                                   "slots_per_entry": MM_SLOTS_PER_ENTRY}},
         "cpu_baseline": cpu,
@@ -961,7 +975,7 @@ def bench_tv(args, torch, binding, dev):
         "rel_l2_vs_oracle": None if rel is None else float("%.3e" % rel),
         "rel_l2_vs_oracle_after_iters": n_par,
         "roofline": {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": round(peak, 3),
-                     "unit": "T VALU lane-slots/s", "frac": round(achieved / peak, 4),
+                     "unit": SLOT_UNIT, "frac": round(achieved / peak, 4),
                      "traffic": stored_traffic(kname, "c1tv",
                                                plan.spgm_plan_launch_shape(B)[0 if kname == "k_fwd_tile" else 1]),
                      "entries_per_launch": int(entries), "slots_per_entry": SLOTS_PER_ENTRY,
