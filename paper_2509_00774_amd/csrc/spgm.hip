@@ -1350,6 +1350,7 @@ struct spgm_plan {
     // shared-geometry batches: packed right-hand sides [tile][z][8][2][64], forward partials
     // [brick run][row][32], packed residuals [row/8][2][64], adjoint partials [split][voxel][32]
     u32x4 *d_mm_s = nullptr;
+    float2 *d_gtab = nullptr;  // G-side brick tables of the A-operand-order batched forward
     float2 *d_mm_part = nullptr;
     u32x4 *d_mm_r = nullptr;
     float2 *d_mm_gpart = nullptr;
@@ -1726,15 +1727,28 @@ template <typename T> int grow_buf(T *&ptr, size_t &cap, size_t need) {
 // launched (each run leaves one partial sum per row and right-hand side).
 struct MMFwdCfg {
     int nrt = 1, rows_wg = 0, n_rb = 0, bpw = 1, n_super = 0;
+    bool rows_form = false;  // k_mm_fwd_rows (entries in A-operand order) instead of k_mm_fwd
     size_t lds = 0;
 };
 
 MMFwdCfg mm_fwd_cfg(const spgm_plan *p, int B) {
     MMFwdCfg c;
     const int A = p->geo.T + p->geo.R;
-    c.nrt = std::min(4, std::max(1, (B + kWaves * kMMRows - 1) / (kWaves * kMMRows)));
-    while (c.nrt > 1 && mm_fwd_lds(c.nrt, A, p->geo.nL) > (size_t)kMaxLds) --c.nrt;
-    c.lds = mm_fwd_lds(c.nrt, A, p->geo.nL);
+    const int want = std::min(4, std::max(1, (B + kWaves * kMMRows - 1) / (kWaves * kMMRows)));
+    // Entries formed in A-operand order need both antennas' brick tables in LDS and the plan's
+    // precomputed L-side table; otherwise the entry tile goes through LDS (k_mm_fwd).
+    if (p->d_ltab && p->geo.ltab_mode == SPGM_PHASE_COMP32) {
+        c.nrt = want;
+        while (c.nrt > 1 && mm_fwd_rows_lds(c.nrt, A, p->geo.nG, p->geo.nL) > (size_t)kMaxLds) --c.nrt;
+        c.rows_form = mm_fwd_rows_lds(c.nrt, A, p->geo.nG, p->geo.nL) <= (size_t)kMaxLds;
+    }
+    if (c.rows_form) {
+        c.lds = mm_fwd_rows_lds(c.nrt, A, p->geo.nG, p->geo.nL);
+    } else {
+        c.nrt = want;
+        while (c.nrt > 1 && mm_fwd_lds(c.nrt, A, p->geo.nL) > (size_t)kMaxLds) --c.nrt;
+        c.lds = mm_fwd_lds(c.nrt, A, p->geo.nL);
+    }
     c.rows_wg = kWaves * kMMRows * c.nrt;
     c.n_rb = (B + c.rows_wg - 1) / c.rows_wg;
     c.bpw = std::max(1, (p->n_tiles * c.n_rb + 255) / 256);
@@ -1779,6 +1793,20 @@ int ensure_mm(spgm_plan *p, int B) {
     const MMAdjCfg ac = mm_adj_cfg(p, B);
     if (!p->d_mm_s && hipMalloc(&p->d_mm_s, sizeof(u32x4) * kMMSlice * kBZ * (size_t)p->n_tiles) != hipSuccess)
         return fail(SPGM_E_NOMEM, "spgm: batched workspace allocation failed");
+    if (fc.rows_form && !p->d_gtab) {
+        // G-side brick tables for the A-operand-order forward, formed once per plan
+        if (hipMalloc(&p->d_gtab, sizeof(float2) * kBrick * (size_t)p->geo.nG * p->n_tiles) != hipSuccess) {
+            p->d_gtab = nullptr;
+            return fail(SPGM_E_NOMEM, "spgm: batched G-side table allocation failed");
+        }
+        hipFuncSetAttribute((const void *)k_build_gtab, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_bytes);
+        k_build_gtab<<<p->n_tiles, kThreads, p->lds_bytes>>>(p->geo, p->d_gtab);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            hipFree(p->d_gtab);
+            p->d_gtab = nullptr;
+            return fail(SPGM_E_DEVICE, "spgm: batched G-side table build failed");
+        }
+    }
     if ((rc = grow_buf(p->d_mm_part, p->mm_part_cap, (size_t)fc.n_super * B * kMMCols))) return rc;
     if ((rc = grow_buf(p->d_mm_r, p->mm_r_cap, (size_t)((B + 7) / 8) * 2 * 64))) return rc;
     if ((rc = grow_buf(p->d_mm_gpart, p->mm_gpart_cap, (size_t)ac.splits * p->N * kMMCols))) return rc;
@@ -1796,6 +1824,28 @@ int mm_forward_pass(spgm_plan *p, const MMFwdCfg &fc, const int4 *srt, int B, co
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
     if (ev) hipEventRecord(ev[0], st);
     const dim3 grid(fc.n_super, fc.n_rb);
+    if (fc.rows_form) {
+        const float4 *gt = reinterpret_cast<const float4 *>(p->d_gtab);
+        switch (fc.nrt) {
+        case 1:
+            k_mm_fwd_rows<PREC, 1><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
+                                                                  p->d_mm_part);
+            break;
+        case 2:
+            k_mm_fwd_rows<PREC, 2><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
+                                                                  p->d_mm_part);
+            break;
+        case 3:
+            k_mm_fwd_rows<PREC, 3><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
+                                                                  p->d_mm_part);
+            break;
+        default:
+            k_mm_fwd_rows<PREC, 4><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
+                                                                  p->d_mm_part);
+        }
+        if (ev) hipEventRecord(ev[1], st);
+        return launch_check("batched forward");
+    }
     switch (fc.nrt) {
     case 1:
         k_mm_fwd<PREC, 1><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, p->d_mm_s, p->d_mm_part);
@@ -2185,6 +2235,12 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
         (const void *)k_mm_fwd<SPGM_MM_FP16, 3>, (const void *)k_mm_fwd<SPGM_MM_FP16, 4>,
         (const void *)k_mm_adj<SPGM_MM_BF16>, (const void *)k_mm_adj<SPGM_MM_FP16>};
     for (const void *k : mm_kernels) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    const void *mm_rows_kernels[] = {
+        (const void *)k_mm_fwd_rows<SPGM_MM_BF16, 1>, (const void *)k_mm_fwd_rows<SPGM_MM_BF16, 2>,
+        (const void *)k_mm_fwd_rows<SPGM_MM_BF16, 3>, (const void *)k_mm_fwd_rows<SPGM_MM_BF16, 4>,
+        (const void *)k_mm_fwd_rows<SPGM_MM_FP16, 1>, (const void *)k_mm_fwd_rows<SPGM_MM_FP16, 2>,
+        (const void *)k_mm_fwd_rows<SPGM_MM_FP16, 3>, (const void *)k_mm_fwd_rows<SPGM_MM_FP16, 4>};
+    for (const void *k : mm_rows_kernels) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     const void *sf_kernels[] = {(const void *)k_sf_fwd<kSFItemsSmall>, (const void *)k_sf_fwd<kSFItems>,
                                 (const void *)k_sf_adj<kSFItemsSmall, 2>, (const void *)k_sf_adj<kSFItems, 4>};
     for (const void *k : sf_kernels)
@@ -2215,6 +2271,7 @@ int spgm_plan_destroy(spgm_plan *p) {
     hipFree(p->d_tv_state);
     hipFree(p->d_vjp_part);
     hipFree(p->d_mm_s);
+    hipFree(p->d_gtab);
     hipFree(p->d_mm_part);
     hipFree(p->d_mm_r);
     hipFree(p->d_mm_gpart);
