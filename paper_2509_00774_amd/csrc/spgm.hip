@@ -1723,54 +1723,70 @@ template <typename T> int grow_buf(T *&ptr, size_t &cap, size_t need) {
 }
 
 // Forward launch shape: rows per wave 32 nrt (nrt = 1..4, fewer when LDS is short), work-groups
-// of 256 nrt rows, bricks grouped into runs so that about one work-group per compute unit is
-// launched (each run leaves one partial sum per row and right-hand side).
+// of 32 nrt rows per wave, bricks grouped into runs so that about one round of work-groups fills
+// the chip (each run leaves one partial sum per row and right-hand side and z range).  By default
+// a work-group has 8 waves over the whole brick; the autotuner may choose 4 waves over two z
+// slices (two work-groups per compute unit) for the A-operand-order form.
 struct MMFwdCfg {
     int nrt = 1, rows_wg = 0, n_rb = 0, bpw = 1, n_super = 0;
-    bool rows_form = false;  // k_mm_fwd_rows (entries in A-operand order) instead of k_mm_fwd
+    int waves = kWaves, zs = kBZ;  // waves per work-group, z slices per work-group
+    bool rows_form = false;        // k_mm_fwd_rows (entries in A-operand order) instead of k_mm_fwd
     size_t lds = 0;
+    int n_slots() const { return n_super * (kBZ / zs); }
 };
 
 MMFwdCfg mm_fwd_cfg(const spgm_plan *p, int B) {
     MMFwdCfg c;
-    const int A = p->geo.T + p->geo.R;
+    const int A = p->geo.T + p->geo.R, nG = p->geo.nG, nL = p->geo.nL;
     const int want = std::min(4, std::max(1, (B + kWaves * kMMRows - 1) / (kWaves * kMMRows)));
+    const int per_cu = 1;  // resident work-groups per compute unit (VGPRs allow 8 waves)
     // Entries formed in A-operand order need both antennas' brick tables in LDS and the plan's
     // precomputed L-side table; otherwise the entry tile goes through LDS (k_mm_fwd).
     if (p->d_ltab && p->geo.ltab_mode == SPGM_PHASE_COMP32) {
         c.nrt = want;
-        while (c.nrt > 1 && mm_fwd_rows_lds(c.nrt, A, p->geo.nG, p->geo.nL) > (size_t)kMaxLds) --c.nrt;
-        c.rows_form = mm_fwd_rows_lds(c.nrt, A, p->geo.nG, p->geo.nL) <= (size_t)kMaxLds;
+        while (c.nrt > 1 && mm_fwd_rows_lds(c.nrt, A, nG, nL) > (size_t)kMaxLds) --c.nrt;
+        c.rows_form = mm_fwd_rows_lds(c.nrt, A, nG, nL) <= (size_t)kMaxLds;
     }
     if (c.rows_form) {
-        c.lds = mm_fwd_rows_lds(c.nrt, A, p->geo.nG, p->geo.nL);
+        c.lds = mm_fwd_rows_lds(c.nrt, A, nG, nL, c.waves, c.zs);
     } else {
         c.nrt = want;
-        while (c.nrt > 1 && mm_fwd_lds(c.nrt, A, p->geo.nL) > (size_t)kMaxLds) --c.nrt;
-        c.lds = mm_fwd_lds(c.nrt, A, p->geo.nL);
+        c.waves = kWaves;
+        c.zs = kBZ;
+        while (c.nrt > 1 && mm_fwd_lds(c.nrt, A, nL) > (size_t)kMaxLds) --c.nrt;
+        c.lds = mm_fwd_lds(c.nrt, A, nL);
     }
-    c.rows_wg = kWaves * kMMRows * c.nrt;
+    c.rows_wg = c.waves * kMMRows * c.nrt;
     c.n_rb = (B + c.rows_wg - 1) / c.rows_wg;
-    c.bpw = std::max(1, (p->n_tiles * c.n_rb + 255) / 256);
+    const int target = 256 * per_cu;
+    c.bpw = std::max(1, (p->n_tiles * c.n_rb * (kBZ / c.zs) + target - 1) / target);
     c.n_super = (p->n_tiles + c.bpw - 1) / c.bpw;
     return c;
 }
 
 // Adjoint launch shape: one work-group per (brick, row range); row ranges are multiples of 512
-// rows (four groups of 128-row rounds), split only when there are fewer than 256 bricks.
+// rows (four row groups of 128 rows), split only when there are fewer than 256 bricks.  Each
+// round stages `stage` rows per group: the whole group when LDS holds it beside the L-side
+// table, else the largest multiple of kMMStage that fits.
 struct MMAdjCfg {
-    int splits = 1, rpw = 0;
+    int splits = 1, rpw = 0, stage = 0;
     size_t lds = 0;
 };
 
 MMAdjCfg mm_adj_cfg(const spgm_plan *p, int B) {
     MMAdjCfg c;
-    const int unit = kMMGroups * kMMStage;
+    const int unit = kMMGroups * 128;
     int splits = std::max(1, (256 + p->n_tiles - 1) / p->n_tiles);
     splits = std::min(splits, (B + unit - 1) / unit);
     c.rpw = ((B + splits - 1) / splits + unit - 1) / unit * unit;
     c.splits = (B + c.rpw - 1) / c.rpw;
-    c.lds = mm_adj_lds(p->geo.T + p->geo.R, p->geo.nL);
+    const int A = p->geo.T + p->geo.R;
+    const int per = (std::min(c.rpw, B) + kMMGroups - 1) / kMMGroups;
+    const size_t fixed = mm_adj_lds(A, p->geo.nL, 0);
+    const int cap = fixed >= (size_t)kMaxLds ? 0
+                    : (int)((kMaxLds - fixed) / (sizeof(float4) * kMMGroups)) / kMMStage * kMMStage;
+    c.stage = std::max(kMMStage, std::min(cap, (per + kMMStage - 1) / kMMStage * kMMStage));
+    c.lds = mm_adj_lds(A, p->geo.nL, c.stage);
     return c;
 }
 
@@ -1807,45 +1823,52 @@ int ensure_mm(spgm_plan *p, int B) {
             return fail(SPGM_E_DEVICE, "spgm: batched G-side table build failed");
         }
     }
-    if ((rc = grow_buf(p->d_mm_part, p->mm_part_cap, (size_t)fc.n_super * B * kMMCols))) return rc;
+    if ((rc = grow_buf(p->d_mm_part, p->mm_part_cap, (size_t)fc.n_slots() * B * kMMCols))) return rc;
     if ((rc = grow_buf(p->d_mm_r, p->mm_r_cap, (size_t)((B + 7) / 8) * 2 * 64))) return rc;
-    if ((rc = grow_buf(p->d_mm_gpart, p->mm_gpart_cap, (size_t)ac.splits * p->N * kMMCols))) return rc;
+    if (ac.splits > 1 && (rc = grow_buf(p->d_mm_gpart, p->mm_gpart_cap, (size_t)ac.splits * p->N * kMMCols)))
+        return rc;  // one split: the adjoint writes its outputs itself
     return SPGM_OK;
 }
 
 // Forward pass of right-hand sides k0 .. k0+K-1 of S ([N][ld]) into the plan's partials.
+// pack = false: the packed operand already holds these right-hand sides (written by the previous
+// step's adjoint).
 template <int PREC>
 int mm_forward_pass(spgm_plan *p, const MMFwdCfg &fc, const int4 *srt, int B, const float2 *S, int ld, int k0,
-                    int K, hipStream_t st) {
-    const size_t nth = (size_t)p->n_tiles * 2048;
-    k_mm_pack_s<PREC><<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(p->geo, S, ld, k0, K, p->n_tiles, p->d_mm_s);
+                    int K, hipStream_t st, bool pack = true) {
     int rc;
-    if ((rc = launch_check("batched pack"))) return rc;
+    if (pack) {
+        const size_t nth = (size_t)p->n_tiles * 2048;
+        k_mm_pack_s<PREC><<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(p->geo, S, ld, k0, K, p->n_tiles, p->d_mm_s);
+        if ((rc = launch_check("batched pack"))) return rc;
+    }
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
     if (ev) hipEventRecord(ev[0], st);
-    const dim3 grid(fc.n_super, fc.n_rb);
     if (fc.rows_form) {
+        const dim3 grid(fc.n_super, fc.n_rb, kBZ / fc.zs);
+        const int nth = fc.waves * kWave;
         const float4 *gt = reinterpret_cast<const float4 *>(p->d_gtab);
         switch (fc.nrt) {
         case 1:
-            k_mm_fwd_rows<PREC, 1><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
-                                                                  p->d_mm_part);
+            k_mm_fwd_rows<PREC, 1><<<grid, nth, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, fc.zs, gt, p->d_mm_s,
+                                                             p->d_mm_part);
             break;
         case 2:
-            k_mm_fwd_rows<PREC, 2><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
-                                                                  p->d_mm_part);
+            k_mm_fwd_rows<PREC, 2><<<grid, nth, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, fc.zs, gt, p->d_mm_s,
+                                                             p->d_mm_part);
             break;
         case 3:
-            k_mm_fwd_rows<PREC, 3><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
-                                                                  p->d_mm_part);
+            k_mm_fwd_rows<PREC, 3><<<grid, nth, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, fc.zs, gt, p->d_mm_s,
+                                                             p->d_mm_part);
             break;
         default:
-            k_mm_fwd_rows<PREC, 4><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, gt, p->d_mm_s,
-                                                                  p->d_mm_part);
+            k_mm_fwd_rows<PREC, 4><<<grid, nth, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, fc.zs, gt, p->d_mm_s,
+                                                             p->d_mm_part);
         }
         if (ev) hipEventRecord(ev[1], st);
         return launch_check("batched forward");
     }
+    const dim3 grid(fc.n_super, fc.n_rb);
     switch (fc.nrt) {
     case 1:
         k_mm_fwd<PREC, 1><<<grid, kThreads, fc.lds, st>>>(p->geo, srt, B, fc.bpw, p->n_tiles, p->d_mm_s, p->d_mm_part);
@@ -1867,26 +1890,29 @@ template <int PREC>
 int mm_row_reduce(spgm_plan *p, const MMFwdCfg &fc, const int4 *srt, const int32_t *rows, int B, const float2 *y,
                   int ldy, int k0, int K, float2 *out, int ldo, bool want_r, hipStream_t st) {
     const int quads = ((B + 7) & ~7) / 4;
-    k_mm_row_reduce<PREC><<<(quads + 7) / 8, 256, 0, st>>>(p->geo, p->d_mm_part, fc.n_super, B, srt, rows, y, ldy, k0,
+    k_mm_row_reduce<PREC><<<(quads + 7) / 8, 256, 0, st>>>(p->geo, p->d_mm_part, fc.n_slots(), B, srt, rows, y, ldy, k0,
                                                             K, out, ldo, want_r ? p->d_mm_r : nullptr);
     return launch_check("batched row reduce");
 }
 
+// Adjoint pass and its outputs: with one row split the adjoint kernel writes g and the proximal
+// update itself (and the next packed operand when s2 is set); otherwise it leaves per-split
+// partials that k_mm_col_reduce sums in a fixed order.
 template <int PREC>
-int mm_adjoint_pass(spgm_plan *p, const MMAdjCfg &ac, const int4 *srt, int B, hipStream_t st) {
+int mm_adjoint_pass(spgm_plan *p, const MMAdjCfg &ac, const int4 *srt, int B, const MMAdjOut &out, hipStream_t st) {
     hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
     if (ev) hipEventRecord(ev[0], st);
-    k_mm_adj<PREC><<<dim3(p->n_tiles, ac.splits), kThreads, ac.lds, st>>>(p->geo, srt, B, ac.rpw, p->d_mm_r,
-                                                                         p->d_mm_gpart, (int)p->N);
+    const bool fused = ac.splits == 1;
+    MMAdjOut o = out;
+    if (!fused) o.s2 = nullptr;
+    k_mm_adj<PREC><<<dim3(p->n_tiles, ac.splits), kThreads, ac.lds, st>>>(
+        p->geo, srt, B, ac.rpw, ac.stage, p->d_mm_r, fused ? nullptr : p->d_mm_gpart, (int)p->N, o);
     if (ev) hipEventRecord(ev[1], st);
-    return launch_check("batched adjoint");
-}
-
-int mm_col_reduce(spgm_plan *p, const MMAdjCfg &ac, int k0, int K, int ld, float2 *g, float2 *s, float step,
-                  float alpha, hipStream_t st) {
+    int rc;
+    if ((rc = launch_check("batched adjoint")) || fused) return rc;
     const size_t nth = (size_t)p->N * kMMCols;
-    k_mm_col_reduce<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(p->d_mm_gpart, ac.splits, (int)p->N, k0, K, ld, g,
-                                                                   s, step, alpha);
+    k_mm_col_reduce<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(p->d_mm_gpart, ac.splits, (int)p->N, out.k0,
+                                                                   out.K, out.ld, out.g, out.s, out.step, out.alpha);
     return launch_check("batched column reduce");
 }
 
@@ -1914,33 +1940,39 @@ int mm_adjoint(spgm_plan *p, const int4 *srt, int B, int K, const float2 *R, flo
         const int quads = ((B + 7) & ~7) / 4;
         k_mm_pack_r<PREC><<<(quads + 7) / 8, 256, 0, st>>>(p->geo, srt, B, R, K, k0, kc, p->d_mm_r);
         if ((rc = launch_check("batched pack"))) return rc;
-        if ((rc = mm_adjoint_pass<PREC>(p, ac, srt, B, st))) return rc;
-        if ((rc = mm_col_reduce(p, ac, k0, kc, K, G, nullptr, 0.f, 0.f, st))) return rc;
+        const MMAdjOut out{k0, kc, K, G, nullptr, 0.f, 0.f, nullptr};
+        if ((rc = mm_adjoint_pass<PREC>(p, ac, srt, B, out, st))) return rc;
     }
     return SPGM_OK;
 }
 
-// One batched SPGM iteration on sorted rows.
+// One batched SPGM iteration on sorted rows.  With K <= 32 and an unsplit adjoint the step can
+// leave the packed operand of its result for the next step (s2_out) and take it from the
+// previous one (packed_in).
 template <int PREC>
 int mm_step(spgm_plan *p, const int4 *srt, const int32_t *rows, int B, int K, const float2 *Ym, float2 *S, float eta,
-            float alpha, hipStream_t st) {
+            float alpha, hipStream_t st, bool packed_in = false, bool s2_out = false) {
     const MMFwdCfg fc = mm_fwd_cfg(p, B);
     const MMAdjCfg ac = mm_adj_cfg(p, B);
     int rc;
     for (int k0 = 0; k0 < K; k0 += kMMCols) {
         const int kc = std::min(kMMCols, K - k0);
-        if ((rc = mm_forward_pass<PREC>(p, fc, srt, B, S, K, k0, kc, st))) return rc;
+        if ((rc = mm_forward_pass<PREC>(p, fc, srt, B, S, K, k0, kc, st, !packed_in))) return rc;
         if ((rc = mm_row_reduce<PREC>(p, fc, srt, rows, B, Ym, K, k0, kc, nullptr, 0, true, st))) return rc;
-        if ((rc = mm_adjoint_pass<PREC>(p, ac, srt, B, st))) return rc;
-        if ((rc = mm_col_reduce(p, ac, k0, kc, K, nullptr, S, eta / (float)B, alpha, st))) return rc;
+        const MMAdjOut out{k0, kc, K, nullptr, S, eta / (float)B, alpha, s2_out ? p->d_mm_s : nullptr};
+        if ((rc = mm_adjoint_pass<PREC>(p, ac, srt, B, out, st))) return rc;
     }
     return SPGM_OK;
 }
 
+// Whether consecutive steps can hand the packed operand on (one pass, unsplit adjoint).
+bool mm_chain_ok(const spgm_plan *p, int B, int K) { return K <= kMMCols && mm_adj_cfg(p, B).splits == 1; }
+
 int mm_step_any(spgm_plan *p, int prec, const int4 *srt, const int32_t *rows, int B, int K, const float2 *Ym,
-                float2 *S, float eta, float alpha, hipStream_t st) {
-    return prec == SPGM_MM_FP16 ? mm_step<SPGM_MM_FP16>(p, srt, rows, B, K, Ym, S, eta, alpha, st)
-                                : mm_step<SPGM_MM_BF16>(p, srt, rows, B, K, Ym, S, eta, alpha, st);
+                float2 *S, float eta, float alpha, hipStream_t st, bool packed_in = false, bool s2_out = false) {
+    return prec == SPGM_MM_FP16
+               ? mm_step<SPGM_MM_FP16>(p, srt, rows, B, K, Ym, S, eta, alpha, st, packed_in, s2_out)
+               : mm_step<SPGM_MM_BF16>(p, srt, rows, B, K, Ym, S, eta, alpha, st, packed_in, s2_out);
 }
 
 // ---------------------------------------------------------------- structured minibatches
@@ -3395,14 +3427,18 @@ int spgm_solve_batched(spgm_plan *p, const int32_t *rows, int32_t iters, int32_t
     const int per = (int)std::max<size_t>(1, std::min<size_t>((size_t)iters, kSolveSortRows / (size_t)B));
     if ((rc = ensure_sorted_batch(p, (size_t)per * B))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    const bool chain = mm_chain_ok(p, B, K);
+    bool packed = false;  // the packed operand holds the current S
     for (int i0 = 0; i0 < iters; i0 += per) {
         const int cnt = std::min(per, iters - i0);
         const int32_t *ri = rows + (size_t)i0 * B;
         if ((rc = run_sort(p, ri, B, cnt, p->d_srt_all, st))) return rc;
         for (int i = 0; i < cnt; ++i) {
+            const bool s2_out = chain && i0 + i + 1 < iters;
             if ((rc = mm_step_any(p, prec, p->d_srt_all + (size_t)i * B, ri + (size_t)i * B, B, K, (const float2 *)Ym,
-                                  (float2 *)S, eta, alpha, st)))
+                                  (float2 *)S, eta, alpha, st, packed, s2_out)))
                 return rc;
+            packed = s2_out;
         }
     }
     return ok();

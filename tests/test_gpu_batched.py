@@ -267,3 +267,37 @@ def test_c0_batched_solve_matches_fp32_reconstruction(bd, prec):
             PREC_NAME[prec], k, nmse_db(Sb[:, k], S_true[:, k]), nmse_db(s32, S_true[:, k]), rel_l2(Sb[:, k], s32)))
     assert worst <= 0.1
     assert plan.status() == 0
+
+
+@pytest.mark.parametrize("K,B,iters", [
+    (8, 256, 5),    # c0 (8 bricks, one row split): each step's adjoint hands the packed S to the next forward
+    (40, 256, 3),   # two passes of right-hand sides: every forward packs S itself
+    (8, 700, 3),    # 8 bricks and 700 rows: the adjoint splits the rows and sums the splits separately
+])
+def test_batched_solve_equals_repeated_steps(bd, K, B, iters):
+    """spgm_solve_batched gives bit for bit the iterates of `iters` separate spgm_step_batched calls
+    on the same row table; with several row splits, one step is also checked against the oracle."""
+    geom = W.config_geometry("c0")
+    orc = Oracle(geom)
+    rng = np.random.default_rng(K * 1000 + B)
+    table = rng.integers(0, orc.M, size=(iters, B)).astype(np.int32)
+    Y = rand_matrix(orc.M, K, 71 + K).astype(np.complex128)
+    S0 = rand_matrix(orc.N, K, 72 + K)
+    steps = json.load(open(os.path.join(ROOT, "tests", "golden", "step_sizes.json")))["c0"]
+    eta = float(np.float32(steps["eta"]))
+    alpha = float(np.float32(0.02 * eta))
+    plan = bd.Plan(geom)
+    Yd = cdev(Y)
+    Ss = cdev(S0)
+    plan.spgm_solve_batched(idev(table), Yd, Ss, eta, alpha, precision=0)
+    St = cdev(S0)
+    for i in range(iters):
+        plan.spgm_step_batched(idev(table[i]), Yd, St, eta, alpha, precision=0)
+        if i == 0 and B > 512:
+            ref = np.stack([orc.step(table[0], Y[:, k], S0[:, k].astype(np.complex128), eta, alpha)
+                            for k in range(K)], axis=1)
+            check_cols(host(St), ref, TOL[0], "c0 batched step, split rows")
+    a, b = host(Ss), host(St)
+    say("K=%d B=%d: solve vs steps max |diff| %.3g" % (K, B, float(np.max(np.abs(a - b)))))
+    assert np.array_equal(a, b)
+    assert plan.status() == 0
