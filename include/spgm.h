@@ -216,6 +216,53 @@ int spgm_unrolled_vjp_step_g(spgm_plan *plan, const int32_t *rows_d, int32_t B, 
 int spgm_plan_autotune(spgm_plan *plan, int32_t B, const char *cache_path, int32_t *fwd_splits,
                        int32_t *adj_splits);
 
+/* Autotuner of the shared-geometry batch kernels (spgm_forward_batched and the calls built on
+ * it) for minibatches of B rows and the given spgm_mm_precision.  The forward candidates are
+ * every combination that fits of: row tiles per wave nrt = 1..4; 8 waves over whole bricks or
+ * (A-operand-order form only) 4 waves over two z slices per work-group; bricks per work-group
+ * half, equal to and twice the default.  The adjoint candidates are row splits of 1, 2 and 4
+ * times the default, each staging all of a work-group's rows at once, 256 or 64 rows per group
+ * and round.  Each side is timed on pseudo-random rows and right-hand sides and the fastest kept
+ * for every later batched call of this plan with this B.  Cached in the same JSON file as
+ * spgm_plan_autotune (cache_path, else SPGM_TUNE_CACHE, else none), key as there plus "|mm" and
+ * the precision, value [nrt, bricks per work-group, waves, z slices, adjoint splits, staged rows,
+ * forward ms, adjoint ms]; a cached key is applied without timing, and a cached shape that does
+ * not fit the plan falls back to the default.  shape (int32_t[7], required) receives the applied
+ * shape as spgm_plan_batched_shape writes it.  Synchronous;
+ * waits for all work on the plan's device first; allocates temporary device memory.  Results of
+ * every candidate agree with the default shape's to the batched path's error bounds (the
+ * adjoint's summation order follows its split). */
+int spgm_plan_autotune_batched(spgm_plan *plan, int32_t B, int32_t precision, const char *cache_path,
+                               int32_t *shape);
+
+/* Launch shape of the shared-geometry batch kernels for minibatches of B rows (the autotuned one,
+ * else the default): shape[0..6] = {row tiles per wave, bricks per work-group, waves per
+ * work-group, z slices per work-group, adjoint row splits, adjoint staged rows per group and
+ * round, 1 if the forward forms entries in A-operand order else 0}.  Host only. */
+int spgm_plan_batched_shape(const spgm_plan *plan, int32_t B, int32_t *shape);
+
+/* The candidates spgm_plan_autotune_batched times for B: forward shapes as int32_t[4] {nrt,
+ * bricks per work-group, waves, z slices} into fwd (up to fwd_cap of them), adjoint shapes as
+ * int32_t[2] {row splits, staged rows} into adj (up to adj_cap); *n_fwd and *n_adj receive the
+ * full counts.  fwd / adj may be NULL to query the counts.  Host only. */
+int spgm_plan_batched_candidates(const spgm_plan *plan, int32_t B, int32_t *fwd, int32_t fwd_cap, int32_t *n_fwd,
+                                 int32_t *adj, int32_t adj_cap, int32_t *n_adj);
+
+/* Autotuner of the structured-minibatch kernels for subsets of nf frequencies, nt transmitters
+ * and nr receivers: times the small-register instances (8 items per thread; only for
+ * nt + nr <= 32 and nt <= 16) against the general ones (16 items) on the forward and adjoint
+ * kernels, and keeps the faster for every later structured call of this plan with this
+ * (nf, nt, nr).  Cached like spgm_plan_autotune (key plus "|sf|nf..|nt..|nr..", value
+ * [items, ms]).  *items (required) receives the applied choice.  Synchronous; waits for all work
+ * on the plan's device first; allocates temporary device memory.  Both instances compute the
+ * same sums in the same order. */
+int spgm_plan_autotune_structured(spgm_plan *plan, int32_t nf, int32_t nt, int32_t nr, const char *cache_path,
+                                  int32_t *items);
+
+/* Items per thread (8 or 16) the structured kernels use for (nf, nt, nr) on this plan.  Host
+ * only. */
+int spgm_plan_structured_shape(const spgm_plan *plan, int32_t nf, int32_t nt, int32_t nr, int32_t *items);
+
 /* Launch shape the tile kernels use for minibatches of B rows on this plan (the autotuned one,
  * else the default): row splits and waves per work-group of the forward and adjoint tile
  * kernels.  Any output pointer may be NULL.  Host only. */
@@ -369,6 +416,17 @@ int spgm_batch_solve(spgm_batch *batch, int32_t iters, const int32_t *B, const i
  * minibatch is cut into ceil(B[i] / rows_per_split) ranges whose column partials are summed in
  * range order (0: 1024, the default; otherwise a positive multiple of 64).  Host only. */
 int spgm_batch_options(spgm_batch *batch, int32_t max_workgroups, int32_t rows_per_split);
+
+/* Autotuner of the ragged batch: for minibatch sizes B[0..n-1] (one per scene, host array),
+ * times one SPGM iteration of the batch with 256, 512, 1024, 2048 and 4096 rows per work item
+ * (the row split of every scene; spgm_batch_options' rows_per_split) on pseudo-random rows and
+ * keeps the fastest for the batch.  Cached like spgm_plan_autotune (key: architecture, phase
+ * mode, number of scenes and a hash of every scene's T, R, F, grid and B; value [rows per work
+ * item, ms]); a cached key is applied without timing.  *rows_per_split (optional) receives the
+ * applied value.  Synchronous; waits for all work on the batch's device first; allocates
+ * temporary device memory.  Results follow the split's summation order (within the batch
+ * path's error bounds of every other split). */
+int spgm_batch_autotune(spgm_batch *batch, const int32_t *B, const char *cache_path, int32_t *rows_per_split);
 
 /* Device-detected row errors of the batch's earlier solves (as spgm_plan_status). */
 int spgm_batch_status(spgm_batch *batch, int32_t *status);

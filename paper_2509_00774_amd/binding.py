@@ -42,7 +42,9 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_forward_structured", "spgm_adjoint_structured", "spgm_step_structured", "spgm_solve_structured",
             "spgm_prox", "spgm_step_reg", "spgm_solve_reg", "spgm_phase_window",
             "spgm_solve_tol", "spgm_batch_options", "spgm_step_noalloc", "spgm_step_grad",
-            "spgm_unrolled_vjp_step_g", "spgm_plan_launch_shape", "spgm_calibrate")
+            "spgm_unrolled_vjp_step_g", "spgm_plan_launch_shape", "spgm_calibrate", "spgm_plan_autotune_batched",
+            "spgm_plan_batched_shape", "spgm_plan_batched_candidates", "spgm_plan_autotune_structured",
+            "spgm_plan_structured_shape", "spgm_batch_autotune")
 
 _dp = C.POINTER(C.c_double)
 
@@ -120,6 +122,13 @@ def load_library(path: str = LIB_PATH):
         "spgm_step_noalloc": [vp, vp, i32, vp, vp, f32, f32, vp],
         "spgm_step_grad": [vp, vp, i32, vp, vp, f32, f32, vp, vp],
         "spgm_plan_launch_shape": [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+        "spgm_plan_autotune_batched": [vp, i32, i32, C.c_char_p, C.POINTER(i32)],
+        "spgm_plan_batched_shape": [vp, i32, C.POINTER(i32)],
+        "spgm_plan_batched_candidates": [vp, i32, C.POINTER(i32), i32, C.POINTER(i32), C.POINTER(i32), i32,
+                                         C.POINTER(i32)],
+        "spgm_plan_autotune_structured": [vp, i32, i32, i32, C.c_char_p, C.POINTER(i32)],
+        "spgm_plan_structured_shape": [vp, i32, i32, i32, C.POINTER(i32)],
+        "spgm_batch_autotune": [vp, C.POINTER(i32), C.c_char_p, C.POINTER(i32)],
         "spgm_calibrate": [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "spgm_unrolled_vjp_step_g": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
         "spgm_solve_tol": [vp, vp, i32, i32, vp, vp, f32, f32, C.c_double, i32, i32, C.POINTER(i32),
@@ -399,6 +408,45 @@ class Plan:
         _check(self._lib.spgm_plan_launch_shape(self._h, int(B), *[C.byref(x) for x in v]))
         return (v[0].value, v[1].value), (v[2].value, v[3].value)
 
+    def spgm_plan_autotune_batched(self, B, precision=MM_BF16, cache_path=None):
+        """Tune the shared-geometry batch kernels for B rows; returns the applied shape as
+        spgm_plan_batched_shape does."""
+        v = (C.c_int32 * 7)()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self._lib.spgm_plan_autotune_batched(self._h, int(B), int(precision), path, v))
+        return tuple(v)
+
+    def spgm_plan_batched_shape(self, B):
+        """(row tiles per wave, bricks per work-group, waves, z slices, adjoint splits, adjoint
+        staged rows, 1 if entries are formed in A-operand order) for minibatches of B rows."""
+        v = (C.c_int32 * 7)()
+        _check(self._lib.spgm_plan_batched_shape(self._h, int(B), v))
+        return tuple(v)
+
+    def spgm_plan_batched_candidates(self, B):
+        """(forward candidates [(nrt, bricks per work-group, waves, z slices)], adjoint candidates
+        [(splits, staged rows)]) that the batched autotuner times for B rows."""
+        nf, na = C.c_int32(), C.c_int32()
+        _check(self._lib.spgm_plan_batched_candidates(self._h, int(B), None, 0, C.byref(nf), None, 0, C.byref(na)))
+        f, a = (C.c_int32 * (4 * max(1, nf.value)))(), (C.c_int32 * (2 * max(1, na.value)))()
+        _check(self._lib.spgm_plan_batched_candidates(self._h, int(B), f, nf.value, C.byref(nf), a, na.value,
+                                                      C.byref(na)))
+        return ([tuple(f[4 * i:4 * i + 4]) for i in range(nf.value)],
+                [tuple(a[2 * i:2 * i + 2]) for i in range(na.value)])
+
+    def spgm_plan_autotune_structured(self, nf, nt, nr, cache_path=None):
+        """Tune the structured kernels for (nf, nt, nr); returns the items per thread applied."""
+        v = C.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self._lib.spgm_plan_autotune_structured(self._h, int(nf), int(nt), int(nr), path, C.byref(v)))
+        return v.value
+
+    def spgm_plan_structured_shape(self, nf, nt, nr):
+        """Items per thread (8 or 16) of the structured kernels for (nf, nt, nr)."""
+        v = C.c_int32()
+        _check(self._lib.spgm_plan_structured_shape(self._h, int(nf), int(nt), int(nr), C.byref(v)))
+        return v.value
+
     def spgm_plan_status(self):
         st = C.c_int32()
         _check(self._lib.spgm_plan_status(self._h, C.byref(st)))
@@ -596,6 +644,17 @@ class Batch:
         _check(self._lib.spgm_batch_status(self._h, C.byref(st)))
         return st.value
 
+    def spgm_batch_autotune(self, Bs, cache_path=None):
+        """Tune the rows per work item for minibatch sizes Bs (one per scene); returns it."""
+        if len(Bs) != self.n:
+            raise ValueError("one minibatch size per scene is required")
+        arr = (C.c_int32 * self.n)(*[int(b) for b in Bs])
+        v = C.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self._lib.spgm_batch_autotune(self._h, arr, path, C.byref(v)))
+        return v.value
+
     solve = spgm_batch_solve
     status = spgm_batch_status
     options = spgm_batch_options
+    autotune = spgm_batch_autotune

@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -1347,6 +1348,12 @@ struct spgm_plan {
     int tile_waves = 8;
     // autotuned launch shapes per minibatch size: B -> (forward, adjoint)
     std::map<int, std::pair<TileShape, TileShape>> tuned;
+    // autotuned shared-geometry batch shapes per B: {row tiles per wave, bricks per work-group,
+    // waves, z slices} of the forward and {row splits, staged rows per round} of the adjoint
+    std::map<int, std::array<int, 4>> mm_fwd_tuned;
+    std::map<int, std::array<int, 2>> mm_adj_tuned;
+    // autotuned structured-minibatch kernels per (nf, nt, nr): items per thread (8 or 16)
+    std::map<std::array<int, 3>, int> sf_tuned;
     // shared-geometry batches: packed right-hand sides [tile][z][8][2][64], forward partials
     // [brick run][row][32], packed residuals [row/8][2][64], adjoint partials [split][voxel][32]
     u32x4 *d_mm_s = nullptr;
@@ -1722,11 +1729,11 @@ template <typename T> int grow_buf(T *&ptr, size_t &cap, size_t need) {
     return SPGM_OK;
 }
 
-// Forward launch shape: rows per wave 32 nrt (nrt = 1..4, fewer when LDS is short), work-groups
-// of 32 nrt rows per wave, bricks grouped into runs so that about one round of work-groups fills
-// the chip (each run leaves one partial sum per row and right-hand side and z range).  By default
-// a work-group has 8 waves over the whole brick; the autotuner may choose 4 waves over two z
-// slices (two work-groups per compute unit) for the A-operand-order form.
+// Forward launch shape: rows per wave 32 nrt (nrt = 1..4), work-groups of 32 nrt rows per wave,
+// bricks grouped into runs of bpw (each run leaves one partial sum per row, right-hand side and
+// z range).  The A-operand-order form (k_mm_fwd_rows) needs the plan's L-side table and both
+// brick tables in LDS; it runs 8 waves over the whole brick or 4 waves over two z slices (two
+// work-groups per compute unit).  k_mm_fwd (entry tile through LDS) runs 8 waves per brick.
 struct MMFwdCfg {
     int nrt = 1, rows_wg = 0, n_rb = 0, bpw = 1, n_super = 0;
     int waves = kWaves, zs = kBZ;  // waves per work-group, z slices per work-group
@@ -1735,58 +1742,97 @@ struct MMFwdCfg {
     int n_slots() const { return n_super * (kBZ / zs); }
 };
 
+// Bricks per work-group that launch about one round of work-groups (8 waves per compute unit).
+int mm_default_bpw(const spgm_plan *p, int n_rb, int waves, int zs) {
+    const int target = 256 * (kWaves / waves);
+    return std::max(1, (p->n_tiles * n_rb * (kBZ / zs) + target - 1) / target);
+}
+
+// The forward shape for explicit choices (bpw = 0: the default for the rest); false if it does
+// not fit this plan.
+bool mm_fwd_shape(const spgm_plan *p, int B, int nrt, int bpw, int waves, int zs, MMFwdCfg &c) {
+    const int A = p->geo.T + p->geo.R, nG = p->geo.nG, nL = p->geo.nL;
+    if (nrt < 1 || nrt > 4 || bpw < 0) return false;
+    c = MMFwdCfg{};
+    const bool rows_ok = p->d_ltab && p->geo.ltab_mode == SPGM_PHASE_COMP32 &&
+                         ((waves == 8 && zs == 4) || (waves == 4 && zs == 2));
+    if (rows_ok && mm_fwd_rows_lds(nrt, A, nG, nL, waves, zs) <= (size_t)kMaxLds) {
+        c.rows_form = true;
+        c.lds = mm_fwd_rows_lds(nrt, A, nG, nL, waves, zs);
+    } else if (waves == kWaves && zs == kBZ && mm_fwd_lds(nrt, A, nL) <= (size_t)kMaxLds) {
+        c.lds = mm_fwd_lds(nrt, A, nL);
+    } else {
+        return false;
+    }
+    c.nrt = nrt;
+    c.waves = waves;
+    c.zs = zs;
+    c.rows_wg = waves * kMMRows * nrt;
+    c.n_rb = (B + c.rows_wg - 1) / c.rows_wg;
+    c.bpw = std::min(p->n_tiles, bpw > 0 ? bpw : mm_default_bpw(p, c.n_rb, waves, zs));
+    c.n_super = (p->n_tiles + c.bpw - 1) / c.bpw;
+    return true;
+}
+
+// The autotuned forward shape for this B if there is one, else 8 waves over whole bricks with as
+// many row tiles per wave (up to 4, one per 256 rows of the minibatch) as LDS allows.
 MMFwdCfg mm_fwd_cfg(const spgm_plan *p, int B) {
     MMFwdCfg c;
-    const int A = p->geo.T + p->geo.R, nG = p->geo.nG, nL = p->geo.nL;
+    const auto it = p->mm_fwd_tuned.find(B);
+    if (it != p->mm_fwd_tuned.end()) {
+        const auto &v = it->second;
+        if (mm_fwd_shape(p, B, v[0], v[1], v[2], v[3], c)) return c;
+    }
     const int want = std::min(4, std::max(1, (B + kWaves * kMMRows - 1) / (kWaves * kMMRows)));
-    const int per_cu = 1;  // resident work-groups per compute unit (VGPRs allow 8 waves)
-    // Entries formed in A-operand order need both antennas' brick tables in LDS and the plan's
-    // precomputed L-side table; otherwise the entry tile goes through LDS (k_mm_fwd).
-    if (p->d_ltab && p->geo.ltab_mode == SPGM_PHASE_COMP32) {
-        c.nrt = want;
-        while (c.nrt > 1 && mm_fwd_rows_lds(c.nrt, A, nG, nL) > (size_t)kMaxLds) --c.nrt;
-        c.rows_form = mm_fwd_rows_lds(c.nrt, A, nG, nL) <= (size_t)kMaxLds;
-    }
-    if (c.rows_form) {
-        c.lds = mm_fwd_rows_lds(c.nrt, A, nG, nL, c.waves, c.zs);
-    } else {
-        c.nrt = want;
-        c.waves = kWaves;
-        c.zs = kBZ;
-        while (c.nrt > 1 && mm_fwd_lds(c.nrt, A, nL) > (size_t)kMaxLds) --c.nrt;
-        c.lds = mm_fwd_lds(c.nrt, A, nL);
-    }
-    c.rows_wg = c.waves * kMMRows * c.nrt;
-    c.n_rb = (B + c.rows_wg - 1) / c.rows_wg;
-    const int target = 256 * per_cu;
-    c.bpw = std::max(1, (p->n_tiles * c.n_rb * (kBZ / c.zs) + target - 1) / target);
-    c.n_super = (p->n_tiles + c.bpw - 1) / c.bpw;
+    for (int nrt = want; nrt >= 1; --nrt)
+        if (mm_fwd_shape(p, B, nrt, 0, kWaves, kBZ, c)) return c;
+    c.lds = (size_t)kMaxLds + 1;  // nothing fits: mm_check refuses
     return c;
 }
 
 // Adjoint launch shape: one work-group per (brick, row range); row ranges are multiples of 512
-// rows (four row groups of 128 rows), split only when there are fewer than 256 bricks.  Each
-// round stages `stage` rows per group: the whole group when LDS holds it beside the L-side
-// table, else the largest multiple of kMMStage that fits.
+// rows (four row groups), by default split only when there are fewer than 256 bricks.  Each
+// round stages `stage` rows per group (a multiple of kMMStage): by default the whole group when
+// LDS holds it beside the L-side table, else the largest multiple that fits.
 struct MMAdjCfg {
     int splits = 1, rpw = 0, stage = 0;
     size_t lds = 0;
 };
 
-MMAdjCfg mm_adj_cfg(const spgm_plan *p, int B) {
-    MMAdjCfg c;
+int mm_default_adj_splits(const spgm_plan *p, int B) {
     const int unit = kMMGroups * 128;
-    int splits = std::max(1, (256 + p->n_tiles - 1) / p->n_tiles);
-    splits = std::min(splits, (B + unit - 1) / unit);
+    const int splits = std::max(1, (256 + p->n_tiles - 1) / p->n_tiles);
+    return std::min(splits, (B + unit - 1) / unit);
+}
+
+// The adjoint shape for explicit choices (stage = 0: as large as useful and LDS allows); false if
+// it does not fit this plan.
+bool mm_adj_shape(const spgm_plan *p, int B, int splits, int stage, MMAdjCfg &c) {
+    const int unit = kMMGroups * 128;
+    if (splits < 1 || stage < 0 || stage % kMMStage != 0) return false;
+    c = MMAdjCfg{};
     c.rpw = ((B + splits - 1) / splits + unit - 1) / unit * unit;
     c.splits = (B + c.rpw - 1) / c.rpw;
     const int A = p->geo.T + p->geo.R;
     const int per = (std::min(c.rpw, B) + kMMGroups - 1) / kMMGroups;
-    const size_t fixed = mm_adj_lds(A, p->geo.nL, 0);
-    const int cap = fixed >= (size_t)kMaxLds ? 0
-                    : (int)((kMaxLds - fixed) / (sizeof(float4) * kMMGroups)) / kMMStage * kMMStage;
-    c.stage = std::max(kMMStage, std::min(cap, (per + kMMStage - 1) / kMMStage * kMMStage));
+    const int full = (per + kMMStage - 1) / kMMStage * kMMStage;
+    if (stage == 0) {
+        const size_t fixed = mm_adj_lds(A, p->geo.nL, 0);
+        const int cap = fixed >= (size_t)kMaxLds
+                            ? 0
+                            : (int)((kMaxLds - fixed) / (sizeof(float4) * kMMGroups)) / kMMStage * kMMStage;
+        stage = std::max(kMMStage, std::min(cap, full));
+    }
+    c.stage = std::min(stage, std::max(kMMStage, full));
     c.lds = mm_adj_lds(A, p->geo.nL, c.stage);
+    return c.lds <= (size_t)kMaxLds;
+}
+
+MMAdjCfg mm_adj_cfg(const spgm_plan *p, int B) {
+    MMAdjCfg c;
+    const auto it = p->mm_adj_tuned.find(B);
+    if (it != p->mm_adj_tuned.end() && mm_adj_shape(p, B, it->second[0], it->second[1], c)) return c;
+    if (!mm_adj_shape(p, B, mm_default_adj_splits(p, B), 0, c)) c.lds = (size_t)kMaxLds + 1;
     return c;
 }
 
@@ -2004,15 +2050,22 @@ int sf_prepare(spgm_plan *p, const SFArgs &a, hipStream_t st) {
     return launch_check("structured rows");
 }
 
-// Subsets of at most 32 antennas in all, at most 16 of them transmitters, take the kernels'
-// small-register instances.
-bool sf_small(const SFArgs &a) { return a.nt + a.nr <= 32 && a.nt <= 16; }
+// Subsets of at most 32 antennas in all, at most 16 of them transmitters, may take the kernels'
+// small-register instances (8 items per thread); they do unless the autotuner chose the general
+// ones (16 items) for this (nf, nt, nr).
+bool sf_small_ok(const SFArgs &a) { return a.nt + a.nr <= 32 && a.nt <= 16; }
+
+bool sf_small(const spgm_plan *p, const SFArgs &a) {
+    if (!sf_small_ok(a)) return false;
+    const auto it = p->sf_tuned.find({a.nf, a.nt, a.nr});
+    return it == p->sf_tuned.end() || it->second == kSFItemsSmall;
+}
 
 int sf_forward_partials(spgm_plan *p, const SFArgs &a, const float2 *s, hipStream_t st) {
     hipEvent_t *ev = timing_slot(p, p->ev_fwd, p->n_fwd);
     if (ev) hipEventRecord(ev[0], st);
     const size_t lds = sf_lds_bytes(p->geo.T + p->geo.R);
-    if (sf_small(a))
+    if (sf_small(p, a))
         k_sf_fwd<kSFItemsSmall><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr, s,
                                                                    p->d_part, a.B);
     else
@@ -2027,7 +2080,7 @@ int sf_adjoint_partials(spgm_plan *p, const SFArgs &a, hipStream_t st) {
     hipEvent_t *ev = timing_slot(p, p->ev_adj, p->n_adj);
     if (ev) hipEventRecord(ev[0], st);
     const size_t lds = sf_lds_bytes(p->geo.T + p->geo.R);
-    if (sf_small(a))
+    if (sf_small(p, a))
         k_sf_adj<kSFItemsSmall, 2><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr,
                                                                       p->d_rs, p->d_gpart, (int)p->N);
     else
@@ -3042,6 +3095,310 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
 }
 
 // ------------------------------------------------------------------------------------------
+// Autotuner of the shared-geometry batch kernels: forward (row tiles per wave, bricks per
+// work-group, waves and z slices per work-group) and adjoint (row splits, staged rows per round)
+// timed separately on pseudo-random rows and right-hand sides, keyed in the same cache.
+// ------------------------------------------------------------------------------------------
+extern "C++" {
+static std::vector<std::array<int, 4>> mm_fwd_candidates(const spgm_plan *p, int B) {
+    std::vector<std::array<int, 4>> out;
+    for (int nrt = 1; nrt <= 4; ++nrt)
+        for (const auto &wz : {std::array<int, 2>{kWaves, kBZ}, std::array<int, 2>{4, 2}}) {
+            MMFwdCfg c;
+            if (!mm_fwd_shape(p, B, nrt, 0, wz[0], wz[1], c)) continue;
+            for (int bpw : {std::max(1, c.bpw / 2), c.bpw, 2 * c.bpw}) {
+                MMFwdCfg d;
+                if (!mm_fwd_shape(p, B, nrt, bpw, wz[0], wz[1], d)) continue;
+                const std::array<int, 4> v{nrt, d.bpw, wz[0], wz[1]};
+                if (std::find(out.begin(), out.end(), v) == out.end()) out.push_back(v);
+            }
+        }
+    return out;
+}
+
+static std::vector<std::array<int, 2>> mm_adj_candidates(const spgm_plan *p, int B) {
+    std::vector<std::array<int, 2>> out;
+    const int d = mm_default_adj_splits(p, B);
+    for (int sp : {d, 2 * d, 4 * d})
+        for (int stage : {0, 4 * kMMStage, kMMStage}) {
+            MMAdjCfg c;
+            if (!mm_adj_shape(p, B, sp, stage, c)) continue;
+            const std::array<int, 2> v{c.splits, c.stage};
+            if (std::find(out.begin(), out.end(), v) == out.end()) out.push_back(v);
+        }
+    return out;
+}
+
+template <int PREC>
+static int mm_tune_time(spgm_plan *p, int B, const float2 *S, const float2 *R, float2 *G, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1, std::array<int, 4> &bf, std::array<int, 2> &ba, double &tf,
+                        double &ta) {
+    int rc = SPGM_OK;
+    auto timed = [&](auto &&launch, float &best) {
+        best = 1e30f;
+        for (int rep = 0; rep < 4 && !rc; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) return (rc = fail(SPGM_E_DEVICE, "autotune: event failed"));
+            if ((rc = launch())) return rc;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                return (rc = fail(SPGM_E_DEVICE, "autotune: timing failed"));
+            if (rep > 0) best = std::min(best, ms);  // the first launch warms up
+        }
+        return rc;
+    };
+    tf = ta = 1e30;
+    bool packed = false;
+    for (const auto &v : mm_fwd_candidates(p, B)) {
+        p->mm_fwd_tuned[B] = v;
+        if ((rc = ensure_mm(p, B))) return rc;
+        const MMFwdCfg fc = mm_fwd_cfg(p, B);
+        if (!packed) {
+            if ((rc = mm_forward_pass<PREC>(p, fc, p->d_srt, B, S, kMMCols, 0, kMMCols, st, true))) return rc;
+            packed = true;
+        }
+        float ms;
+        if (timed([&] { return mm_forward_pass<PREC>(p, fc, p->d_srt, B, S, kMMCols, 0, kMMCols, st, false); }, ms))
+            return rc;
+        if (ms < tf) {
+            tf = ms;
+            bf = v;
+        }
+    }
+    p->mm_fwd_tuned[B] = bf;
+    const int quads = ((B + 7) & ~7) / 4;
+    k_mm_pack_r<PREC><<<(quads + 7) / 8, 256, 0, st>>>(p->geo, p->d_srt, B, R, kMMCols, 0, kMMCols, p->d_mm_r);
+    if ((rc = launch_check("autotune pack"))) return rc;
+    for (const auto &v : mm_adj_candidates(p, B)) {
+        p->mm_adj_tuned[B] = v;
+        if ((rc = ensure_mm(p, B))) return rc;
+        const MMAdjCfg ac = mm_adj_cfg(p, B);
+        const MMAdjOut out{0, kMMCols, kMMCols, G, nullptr, 0.f, 0.f, nullptr};
+        float ms;
+        if (timed([&] { return mm_adjoint_pass<PREC>(p, ac, p->d_srt, B, out, st); }, ms)) return rc;
+        if (ms < ta) {
+            ta = ms;
+            ba = v;
+        }
+    }
+    p->mm_adj_tuned[B] = ba;
+    return rc;
+}
+
+}  // extern "C++"
+
+int spgm_plan_autotune_batched(spgm_plan *p, int32_t B, int32_t prec, const char *cache_path, int32_t *shape) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm_plan_autotune_batched: plan is NULL");
+    if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm_plan_autotune_batched: B=%d outside [1, %d]", B, kMaxB);
+    if (prec != SPGM_MM_BF16 && prec != SPGM_MM_FP16)
+        return fail(SPGM_E_INVALID, "spgm_plan_autotune_batched: unknown precision %d", prec);
+    if (p->phase_mode != SPGM_PHASE_COMP32)
+        return fail(SPGM_E_UNSUPPORTED, "spgm_plan_autotune_batched: needs a plan created with SPGM_PHASE_COMP32");
+    DeviceGuard guard(p->device);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_autotune_batched: device error");
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
+    const std::string key = tune_key(p, B) + "|mm" + std::to_string(prec);
+    std::map<std::string, std::vector<double>> cache;
+    if (!path.empty()) cache = read_cache(path);
+    const auto hit = cache.find(key);
+    int rc = SPGM_OK;
+    if (hit != cache.end() && hit->second.size() >= 6) {
+        const auto &v = hit->second;
+        p->mm_fwd_tuned[B] = {(int)v[0], (int)v[1], (int)v[2], (int)v[3]};
+        p->mm_adj_tuned[B] = {(int)v[4], (int)v[5]};
+    } else {
+        // timing inputs: uniform pseudo-random rows (xorshift) and right-hand sides
+        uint64_t x = 0x2545F4914F6CDD1Dull ^ (uint64_t)B;
+        auto next = [&x]() {
+            x ^= x << 13;
+            x ^= x >> 7;
+            x ^= x << 17;
+            return x;
+        };
+        std::vector<int32_t> hrows(B);
+        for (int i = 0; i < B; ++i) hrows[i] = (int32_t)(next() % (uint64_t)p->M);
+        const size_t ns = (size_t)p->N * kMMCols, nr = (size_t)B * kMMCols;
+        std::vector<float2> hv(std::max(ns, nr));
+        for (auto &v : hv) {
+            const uint64_t r = next();
+            v = make_float2((float)((r >> 11) % 2001) / 1000.f - 1.f, (float)((r >> 33) % 2001) / 1000.f - 1.f);
+        }
+        int32_t *drows = nullptr;
+        float2 *dS = nullptr, *dR = nullptr, *dG = nullptr;
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipMalloc(&drows, sizeof(int32_t) * B) != hipSuccess || hipMalloc(&dS, sizeof(float2) * ns) != hipSuccess ||
+            hipMalloc(&dR, sizeof(float2) * nr) != hipSuccess || hipMalloc(&dG, sizeof(float2) * ns) != hipSuccess ||
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess)
+            rc = fail(SPGM_E_NOMEM, "spgm_plan_autotune_batched: allocation failed");
+        if (!rc && (hipMemcpy(drows, hrows.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(dS, hv.data(), sizeof(float2) * ns, hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(dR, hv.data(), sizeof(float2) * nr, hipMemcpyHostToDevice) != hipSuccess))
+            rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune_batched: copy failed");
+        if (!rc) rc = ensure_workspace(p, B);
+        if (!rc) rc = run_sort(p, drows, B, 1, p->d_srt, st);
+        std::array<int, 4> bf{};
+        std::array<int, 2> ba{};
+        double tf = 0.0, ta = 0.0;
+        const bool timing = p->timing;
+        p->timing = false;
+        if (!rc)
+            rc = prec == SPGM_MM_FP16 ? mm_tune_time<SPGM_MM_FP16>(p, B, dS, dR, dG, st, e0, e1, bf, ba, tf, ta)
+                                      : mm_tune_time<SPGM_MM_BF16>(p, B, dS, dR, dG, st, e0, e1, bf, ba, tf, ta);
+        p->timing = timing;
+        if (st) hipStreamSynchronize(st);
+        hipFree(drows);
+        hipFree(dS);
+        hipFree(dR);
+        hipFree(dG);
+        if (st) hipStreamDestroy(st);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (rc) {
+            p->mm_fwd_tuned.erase(B);
+            p->mm_adj_tuned.erase(B);
+            return rc;
+        }
+        if (!path.empty()) {
+            cache[key] = {(double)bf[0], (double)bf[1], (double)bf[2], (double)bf[3], (double)ba[0], (double)ba[1],
+                          tf, ta};
+            write_cache(path, cache);
+        }
+    }
+    if (mm_fwd_cfg(p, B).lds > (size_t)kMaxLds || mm_adj_cfg(p, B).lds > (size_t)kMaxLds)
+        return fail(SPGM_E_UNSUPPORTED, "spgm_plan_autotune_batched: brick tables exceed LDS");
+    if ((rc = ensure_mm(p, B))) return rc;
+    return spgm_plan_batched_shape(p, B, shape);
+}
+
+int spgm_plan_batched_shape(const spgm_plan *p, int32_t B, int32_t *shape) {
+    if (!p || !shape) return fail(SPGM_E_INVALID, "spgm_plan_batched_shape: plan and shape must be non-NULL");
+    if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm_plan_batched_shape: B=%d outside [1, %d]", B, kMaxB);
+    const MMFwdCfg f = mm_fwd_cfg(p, B);
+    const MMAdjCfg a = mm_adj_cfg(p, B);
+    const int32_t v[7] = {f.nrt, f.bpw, f.waves, f.zs, a.splits, a.stage, f.rows_form ? 1 : 0};
+    std::memcpy(shape, v, sizeof(v));
+    return ok();
+}
+
+int spgm_plan_batched_candidates(const spgm_plan *p, int32_t B, int32_t *fwd, int32_t fwd_cap, int32_t *n_fwd,
+                                 int32_t *adj, int32_t adj_cap, int32_t *n_adj) {
+    if (!p || !n_fwd || !n_adj) return fail(SPGM_E_INVALID, "spgm_plan_batched_candidates: NULL argument");
+    if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm_plan_batched_candidates: B=%d outside [1, %d]", B, kMaxB);
+    const auto f = mm_fwd_candidates(p, B);
+    const auto a = mm_adj_candidates(p, B);
+    *n_fwd = (int32_t)f.size();
+    *n_adj = (int32_t)a.size();
+    for (int i = 0; fwd && i < std::min((int)f.size(), fwd_cap); ++i)
+        for (int k = 0; k < 4; ++k) fwd[4 * i + k] = f[i][k];
+    for (int i = 0; adj && i < std::min((int)a.size(), adj_cap); ++i)
+        for (int k = 0; k < 2; ++k) adj[2 * i + k] = a[i][k];
+    return ok();
+}
+
+// ------------------------------------------------------------------------------------------
+// Autotuner of the structured-minibatch kernels: the small-register instances (8 items per
+// thread, for nt + nr <= 32 and nt <= 16) or the general ones (16 items), timed on the forward
+// and adjoint kernels of subsets of the first nf frequencies, nt transmitters and nr receivers.
+// ------------------------------------------------------------------------------------------
+int spgm_plan_autotune_structured(spgm_plan *p, int32_t nf, int32_t nt, int32_t nr, const char *cache_path,
+                                  int32_t *items) {
+    if (!p) return fail(SPGM_E_INVALID, "spgm_plan_autotune_structured: plan is NULL");
+    if (nf < 1 || nt < 1 || nr < 1 || nf > p->geo.F || nt > p->geo.T || nr > p->geo.R)
+        return fail(SPGM_E_INVALID, "spgm_plan_autotune_structured: need 1 <= nf <= F, 1 <= nt <= T, 1 <= nr <= R");
+    DeviceGuard guard(p->device);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_autotune_structured: device error");
+    std::vector<int32_t> idx(std::max(nf, std::max(nt, nr)));
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int32_t)i;
+    int32_t *d_idx = nullptr;
+    if (hipMalloc(&d_idx, sizeof(int32_t) * idx.size()) != hipSuccess)
+        return fail(SPGM_E_NOMEM, "spgm_plan_autotune_structured: allocation failed");
+    if (hipMemcpy(d_idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(d_idx);
+        return fail(SPGM_E_DEVICE, "spgm_plan_autotune_structured: copy failed");
+    }
+    const SFArgs a{d_idx, d_idx, d_idx, nf, nt, nr, nf * nt * nr};
+    int rc = sf_check(p, a, "spgm_plan_autotune_structured");
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
+    std::ostringstream ks;
+    ks << tune_key(p, a.B) << "|sf|nf" << nf << "|nt" << nt << "|nr" << nr;
+    const std::string key = ks.str();
+    std::map<std::string, std::vector<double>> cache;
+    if (!rc && !path.empty()) cache = read_cache(path);
+    const auto hit = cache.find(key);
+    const std::array<int, 3> sk{nf, nt, nr};
+    if (!rc && hit != cache.end() && !hit->second.empty()) {
+        const int v = (int)hit->second[0];
+        p->sf_tuned[sk] = (v == kSFItemsSmall && sf_small_ok(a)) ? kSFItemsSmall : kSFItems;
+    } else if (!rc) {
+        float2 *ds = nullptr;
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipMalloc(&ds, sizeof(float2) * p->N) != hipSuccess ||
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess)
+            rc = fail(SPGM_E_NOMEM, "spgm_plan_autotune_structured: allocation failed");
+        if (!rc && hipMemsetAsync(ds, 0, sizeof(float2) * p->N, st) != hipSuccess)
+            rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune_structured: fill failed");
+        if (!rc) rc = sf_prepare(p, a, st);
+        if (!rc && hipMemsetAsync(p->d_rs, 0, sizeof(float2) * a.B, st) != hipSuccess)
+            rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune_structured: fill failed");
+        const bool timing = p->timing;
+        p->timing = false;
+        double best = 1e30;
+        int best_items = kSFItems;
+        for (int cand : {kSFItemsSmall, kSFItems}) {
+            if (rc) break;
+            if (cand == kSFItemsSmall && !sf_small_ok(a)) continue;
+            p->sf_tuned[sk] = cand;
+            float tbest = 1e30f;
+            for (int rep = 0; rep < 4 && !rc; ++rep) {
+                float ms = 0.f;
+                if (hipEventRecord(e0, st) != hipSuccess) rc = fail(SPGM_E_DEVICE, "autotune: event failed");
+                if (!rc) rc = sf_forward_partials(p, a, ds, st);
+                if (!rc) rc = sf_adjoint_partials(p, a, st);
+                if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = fail(SPGM_E_DEVICE, "spgm_plan_autotune_structured: timing failed");
+                if (!rc && rep > 0) tbest = std::min(tbest, ms);
+            }
+            if (!rc && tbest < best) {
+                best = tbest;
+                best_items = cand;
+            }
+        }
+        p->timing = timing;
+        if (st) hipStreamSynchronize(st);
+        hipFree(ds);
+        if (st) hipStreamDestroy(st);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (rc) {
+            p->sf_tuned.erase(sk);
+        } else {
+            p->sf_tuned[sk] = best_items;
+            if (!path.empty()) {
+                cache[key] = {(double)best_items, best};
+                write_cache(path, cache);
+            }
+        }
+    }
+    hipFree(d_idx);
+    if (rc) return rc;
+    return spgm_plan_structured_shape(p, nf, nt, nr, items);
+}
+
+int spgm_plan_structured_shape(const spgm_plan *p, int32_t nf, int32_t nt, int32_t nr, int32_t *items) {
+    if (!p || !items) return fail(SPGM_E_INVALID, "spgm_plan_structured_shape: plan and items must be non-NULL");
+    const SFArgs a{nullptr, nullptr, nullptr, nf, nt, nr, nf * nt * nr};
+    *items = sf_small(p, a) ? kSFItemsSmall : kSFItems;
+    return ok();
+}
+
+// ------------------------------------------------------------------------------------------
 // Ragged batches
 // ------------------------------------------------------------------------------------------
 int spgm_batch_create(spgm_batch **out, const spgm_geometry *geoms, int32_t n, int32_t phase_mode) {
@@ -3312,6 +3669,117 @@ int spgm_plan_launch_shape(const spgm_plan *p, int32_t B, int32_t *fwd_splits, i
     if (fwd_waves) *fwd_waves = f.waves;
     if (adj_splits) *adj_splits = a.splits;
     if (adj_waves) *adj_waves = a.waves;
+    return ok();
+}
+
+// Autotuner of the ragged batch: rows per work item (the row split of every scene) among 256,
+// 512, 1024, 2048 and 4096, timed on one SPGM iteration over pseudo-random rows of the given
+// minibatch sizes; cached in the same file, keyed by architecture, phase mode and a hash of
+// every scene's (T, R, F, grid, B).
+int spgm_batch_autotune(spgm_batch *b, const int32_t *B, const char *cache_path, int32_t *rows_per_split) {
+    if (!b || !B) return fail(SPGM_E_INVALID, "spgm_batch_autotune: batch and B must be non-NULL");
+    const int n = (int)b->plans.size();
+    for (int i = 0; i < n; ++i)
+        if (B[i] < 1 || B[i] > kMaxB) return fail(SPGM_E_INVALID, "spgm_batch_autotune: scene %d: B=%d out of range", i, B[i]);
+    DeviceGuard guard(b->device);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_batch_autotune: device error");
+    // cache key: architecture, phase mode and every scene's (T, R, F, grid, B)
+    std::ostringstream k;
+    {
+        hipDeviceProp_t prop;
+        std::string arch = "unknown";
+        if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+        uint64_t h = 1469598103934665603ull;  // FNV-1a over the scene shapes
+        for (int i = 0; i < n; ++i) {
+            const Geo &g = b->plans[i]->geo;
+            const int v[7] = {g.T, g.R, g.F, g.nx, g.ny, g.nz, B[i]};
+            for (int x : v) {
+                h ^= (uint64_t)(uint32_t)x;
+                h *= 1099511628211ull;
+            }
+        }
+        k << arch << "|batch|phase" << b->phase_mode << "|n" << n << "|h" << std::hex << h;
+    }
+    std::string path = cache_path ? cache_path : "";
+    if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
+    std::map<std::string, std::vector<double>> cache;
+    if (!path.empty()) cache = read_cache(path);
+    const auto hit = cache.find(k.str());
+    if (hit != cache.end() && !hit->second.empty()) {
+        const int r = (int)hit->second[0];
+        b->rows_per_split = (r > 0 && r % kWave == 0) ? r : kBatchRowsPerSplit;
+    } else {
+        // timing inputs per scene: uniform pseudo-random rows, measurements and a zero iterate
+        std::vector<int32_t *> rows(n, nullptr);
+        std::vector<float2 *> ys(n, nullptr), ss(n, nullptr);
+        int rc = SPGM_OK;
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (int i = 0; i < n && !rc; ++i) {
+            const spgm_plan *p = b->plans[i];
+            std::vector<int32_t> hr(B[i]);
+            for (int j = 0; j < B[i]; ++j) {
+                x ^= x << 13;
+                x ^= x >> 7;
+                x ^= x << 17;
+                hr[j] = (int32_t)(x % (uint64_t)p->M);
+            }
+            if (hipMalloc(&rows[i], sizeof(int32_t) * B[i]) != hipSuccess ||
+                hipMalloc(&ys[i], sizeof(float2) * (size_t)p->M) != hipSuccess ||
+                hipMalloc(&ss[i], sizeof(float2) * (size_t)p->N) != hipSuccess)
+                rc = fail(SPGM_E_NOMEM, "spgm_batch_autotune: allocation failed");
+            else if (hipMemcpy(rows[i], hr.data(), sizeof(int32_t) * B[i], hipMemcpyHostToDevice) != hipSuccess ||
+                     hipMemset(ys[i], 0, sizeof(float2) * (size_t)p->M) != hipSuccess ||
+                     hipMemset(ss[i], 0, sizeof(float2) * (size_t)p->N) != hipSuccess)
+                rc = fail(SPGM_E_DEVICE, "spgm_batch_autotune: copy failed");
+        }
+        std::vector<float> eta(n, 1.f), alpha(n, 0.f);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+            rc = fail(SPGM_E_NOMEM, "spgm_batch_autotune: event creation failed");
+        const int saved_wg = b->max_wg;
+        b->max_wg = 0;
+        double best = 1e30;
+        int best_r = kBatchRowsPerSplit;
+        for (int r : {256, 512, 1024, 2048, 4096}) {
+            if (rc) break;
+            b->rows_per_split = r;
+            float tbest = 1e30f;
+            for (int rep = 0; rep < 3 && !rc; ++rep) {
+                hipEventRecord(e0, nullptr);
+                rc = spgm_batch_solve(b, 1, B, rows.data(), (const void *const *)ys.data(), (void *const *)ss.data(),
+                                      eta.data(), alpha.data(), 0, nullptr);
+                float ms = 0.f;
+                if (!rc && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = fail(SPGM_E_DEVICE, "spgm_batch_autotune: timing failed");
+                if (!rc && rep > 0) tbest = std::min(tbest, ms);
+            }
+            if (!rc && tbest < best) {
+                best = tbest;
+                best_r = r;
+            }
+        }
+        b->max_wg = saved_wg;
+        for (int i = 0; i < n; ++i) {
+            hipFree(rows[i]);
+            hipFree(ys[i]);
+            hipFree(ss[i]);
+        }
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (rc) {
+            b->rows_per_split = kBatchRowsPerSplit;
+            return rc;
+        }
+        b->rows_per_split = best_r;
+        if (!path.empty()) {
+            cache[k.str()] = {(double)best_r, best};
+            write_cache(path, cache);
+        }
+    }
+    if (rows_per_split) *rows_per_split = b->rows_per_split;
     return ok();
 }
 
