@@ -575,6 +575,9 @@ def bench_ragged(args, torch, binding, dev):
         etas.append(eta)
         alphas.append(float(np.float32(steps[i]["lambda"] * eta)))
         s_true.append(st)
+    rps = None if args.no_tune else batch.autotune([sc["B"] for sc in scenes])
+    if rps:
+        log("ragged batch: %d rows per work item (autotuned)" % rps)
     ss = [torch.zeros(sc["N"], dtype=torch.complex64, device=dev) for sc in scenes]
     # parity sample: the first two iterations of every scene from zero
     s_par1 = [torch.zeros(sc["N"], dtype=torch.complex64, device=dev) for sc in scenes]
@@ -641,7 +644,8 @@ def bench_ragged(args, torch, binding, dev):
         "config": {"workload": "c3: ragged batch of %d scenes (T, R in 8..32, F in 16..64, grids 16x16x8..64x64x32, "
                                "B = ceil(M/4)), l1 weight 5%% of each scene's lambda_max, one launch per phase, "
                                "whole solve in one HIP graph" % len(scenes),
-                   "scenes": len(scenes), "sum_BN": int(entries)},
+                   "scenes": len(scenes), "sum_BN": int(entries),
+                   "launch_shape": {"rows_per_work_item": rps or 1024, "autotuned": rps is not None}},
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if not errs1 else float("%.3e" % max(list(errs1.values()) + list(errs2.values()))),
         "rel_l2_vs_oracle_iter1_1pct_voxels_per_scene": {str(i): float("%.3e" % e) for i, e in errs1.items()},
@@ -680,6 +684,9 @@ def bench_batched(args, torch, binding, dev):
     alpha = float(np.float32(sj["lambda"] * eta))
     log("batched c1 x %d scenes: M=%d N=%d B=%d; drawing %d minibatches" % (Kr, M, N, B, Wm + steps))
     plan = binding.Plan(geom)
+    shape = plan.spgm_plan_batched_shape(B) if args.no_tune else plan.spgm_plan_autotune_batched(B, prec)
+    log("batched launch shape%s: forward %d row tiles per wave, %d bricks per work-group, %d waves over %d z slices; "
+        "adjoint %d splits, %d staged rows" % ((" (autotuned)" if not args.no_tune else "",) + tuple(shape[:6])))
     all_rows = torch.arange(M, dtype=torch.int32, device=dev)
     S_true = np.zeros((N, Kr), dtype=np.complex64)
     Y = np.zeros((M, Kr), dtype=np.complex64)
@@ -758,7 +765,10 @@ def bench_batched(args, torch, binding, dev):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "c1 geometry (32 Tx + 32 Rx, 64 frequencies, 64x64x32 voxels, B=4096) with K=32 "
                                "scenes sharing the minibatch; batched SPGM step, bfloat16 operands, float32 accumulation",
-                   "M": M, "N": N, "B": B, "K": Kr},
+                   "M": M, "N": N, "B": B, "K": Kr,
+                   "launch_shape": {"fwd_row_tiles_per_wave": shape[0], "fwd_bricks_per_wg": shape[1],
+                                    "fwd_waves": shape[2], "fwd_z_slices": shape[3], "adj_splits": shape[4],
+                                    "adj_staged_rows": shape[5], "autotuned": not args.no_tune}},
         "spgm_iters_per_s": round(steps / dt, 2),
         "scene_iters_per_s": round(Kr * steps / dt, 1),
         "float32_scene_iters_per_s": round(Kr * steps / t_f, 1),
@@ -801,6 +811,9 @@ def bench_structured(args, torch, binding, dev):
                                            seed=cfg["seed"] + 7)
     s_true, idx = W.config_scene("c1")
     plan = binding.Plan(geom)
+    items = (plan.spgm_plan_structured_shape(nf, nt, nr) if args.no_tune
+             else plan.spgm_plan_autotune_structured(nf, nt, nr))
+    log("structured kernels: %d items per thread%s" % (items, "" if args.no_tune else " (autotuned)"))
     all_rows = torch.arange(M, dtype=torch.int32, device=dev)
     y0 = plan.spgm_forward(all_rows, torch.from_numpy(s_true.astype(np.complex64)).to(dev))
     y_host = W.add_noise(y0.cpu().numpy().astype(np.complex128), cfg["snr_db"], seed=cfg["seed"] + 2)
@@ -862,7 +875,8 @@ def bench_structured(args, torch, binding, dev):
         "config": {"workload": "c1 geometry (32 Tx + 32 Rx, 64 frequencies, 64x64x32 voxels) with structured "
                                "minibatches of 16 frequencies x 16 Tx x 16 Rx (B=4096); separable factorisation, "
                                "float32 GEMMs on the matrix cores", "M": M, "N": N, "B": B,
-                   "structured": [nf, nt, nr]},
+                   "structured": [nf, nt, nr],
+                   "launch_shape": {"items_per_thread": items, "autotuned": not args.no_tune}},
         "spgm_iters_per_s": round(K / dt, 2),
         "rel_l2_vs_oracle": None if rel is None else float("%.3e" % rel),
         "rel_l2_vs_oracle_after_iters": n_par,
