@@ -177,6 +177,54 @@ int spgm_solve_tol(spgm_plan *plan, const int32_t *rows_d, int32_t iters, int32_
                    void *s_d, float eta, float alpha, double tol, int32_t check_every, int32_t use_graph,
                    int32_t *iters_done, double *changes, void *stream);
 
+/* Seeded minibatches (Sec. IV: each SPGM iteration draws its minibatch of rows uniformly at
+ * random).  The generator is SplitMix64 (Steele, Lea and Flood, OOPSLA 2014: state += 0x9E3779B9
+ * 7F4A7C15; z = state; z = (z ^ z>>30) * 0xBF58476D1CE4E5B9; z = (z ^ z>>27) *
+ * 0x94D049BB133111EB; output z ^ z>>31).  Iteration k (global index: start_iter + i) takes
+ * outputs u_1, u_2, ... number k 2^32 + 1, k 2^32 + 2, ... of the sequence whose initial state is
+ * `seed`, i.e. it starts from state seed + k 2^32 0x9E3779B97F4A7C15 (mod 2^64).  A partial
+ * Fisher-Yates shuffle of the identity 0 .. n-1 turns draws into m distinct indices: for
+ * j = 0 .. m-1, position j is swapped with position j + floor((u_{j+1} >> 32) (n - j) / 2^32) and
+ * index j is the value position j then holds.  Uniform rows: n = M, m = B.  Structured subsets
+ * (Sec. IV-A): the same iteration stream draws nf of F frequencies, then nt of T transmitters,
+ * then nr of R receivers.  Host only, no device memory. */
+int spgm_rows_generate(uint64_t seed, int32_t start_iter, int32_t iters, int64_t M, int32_t B,
+                       int32_t *rows_out /* host int32[iters][B] */);
+int spgm_subsets_generate(uint64_t seed, int32_t start_iter, int32_t iters, int32_t F, int32_t T, int32_t R,
+                          int32_t nf, int32_t nt, int32_t nr, int32_t *f_out /* host int32[iters][nf] */,
+                          int32_t *t_out /* host int32[iters][nt] */, int32_t *r_out /* host int32[iters][nr] */);
+
+/* Options of spgm_solve_ex (initialise with spgm_solve_opts_init, then set fields). */
+typedef struct spgm_solve_opts {
+    int32_t iters;         /* iterations to run, >= 0 */
+    int32_t B;             /* rows per minibatch (sampling 0), 1 <= B <= 2^24 (and <= M when drawn) */
+    double lambda;         /* l1 weight of Eq. 3, >= 0 */
+    double eta;            /* step size, > 0; the threshold is alpha = lambda * eta (Eq. 5) */
+    const int32_t *rows_d; /* device int32[iters][B] minibatches, or NULL: drawn by the generator */
+    uint64_t seed;         /* generator seed (rows_d == NULL) */
+    int32_t sampling;      /* 0: uniform rows; 1: structured subsets (nf x nt x nr, generator only) */
+    int32_t nf, nt, nr;    /* structured subset sizes (sampling 1) */
+    int32_t start_iter;    /* global index of the first iteration (generator stream), >= 0 */
+    double tol;            /* > 0: stop at the termination rule as spgm_solve_tol; 0: all iterations */
+    int32_t check_every;   /* iterations per termination check (tol > 0); default 50 */
+    int32_t use_graph;     /* 1: replay captured HIP graphs (as spgm_solve_graph / spgm_solve_tol) */
+    int32_t *iters_done;   /* optional host out: iterations performed */
+} spgm_solve_opts;
+
+/* Defaults: every field zero except check_every = 50. */
+int spgm_solve_opts_init(spgm_solve_opts *opts);
+
+/* SPGM solve (Eq. 5 iterated) with options: the minibatches are opts->rows_d or drawn by the
+ * generator above for iterations start_iter .. start_iter + iters - 1 (so a solve split over
+ * several calls with matching start_iter reproduces one call bit for bit); uniform rows run as
+ * spgm_solve, spgm_solve_graph (use_graph) or spgm_solve_tol (tol > 0); structured subsets run as
+ * spgm_solve_structured (fixed iterations, no graph: SPGM_E_UNSUPPORTED otherwise).  Drawn
+ * minibatches are made on the host in chunks of up to 2^22 rows, copied to a device buffer the
+ * plan keeps (through two pinned host buffers, so drawing the next chunk overlaps the device
+ * work) and consumed on `stream`; the call returns when the last chunk is queued (after the stop
+ * is known when tol > 0).  Errors as the solve it runs; SPGM_E_INVALID for bad options. */
+int spgm_solve_ex(spgm_plan *plan, const void *y_d, void *s_d, const spgm_solve_opts *opts, void *stream);
+
 /* Backward of one unrolled SPGM iteration (differentiation of Eq. 5 with the gradient of
  * Eq. 6 with respect to its input iterate, step size and threshold):
  *     z = s - (eta/B) A_B^H (A_B s - y_B),   s' = S_tau(z)    (S as in spgm_step, tau = alpha).

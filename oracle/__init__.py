@@ -22,6 +22,10 @@ Functions and the passage each one follows:
 * :func:`nmse`, :func:`psnr_magnitude`                   -- error metrics (Sec. V, PSNR over normalised magnitudes)
 * :func:`unrolled_forward`, :func:`unrolled_vjp`         -- K iterations of Eq. 5 with per-iteration step size
                                                             and threshold, and their chain-rule gradient
+* :func:`splitmix64`, :func:`rows_generate`,
+  :func:`subsets_generate`                               -- the seeded minibatch draw of each SPGM iteration
+                                                            (Sec. IV: rows drawn uniformly at random), written
+                                                            from the generator's published definition
 """
 from __future__ import annotations
 
@@ -373,3 +377,63 @@ def unrolled_vjp(orc, rows_table, y, iterates, eta, tau, sbar):
         eta_bar[k] = -np.real(np.vdot(zbar, g)) / B
         sbar = zbar - (float(eta[k]) / B) * orc.adjoint(rows, orc.forward(rows, zbar))
     return sbar, eta_bar, tau_bar
+
+
+# ------------------------------------------------------------------------------------------
+# Seeded minibatches (Sec. IV: every SPGM iteration draws its rows uniformly at random).
+# SplitMix64 as published by Steele, Lea and Flood (OOPSLA 2014); iteration k of a solve uses
+# outputs k * 2**32 + 1, k * 2**32 + 2, ... of the sequence seeded with `seed`; a partial
+# Fisher-Yates shuffle of 0 .. n-1 maps the draws to m distinct indices (draw j swaps position j
+# with position j + floor(hi32(u) * (n - j) / 2**32)).  Plain Python integers, small cases only.
+# ------------------------------------------------------------------------------------------
+_MASK64 = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64(state: int):
+    """Generator of SplitMix64 outputs from the initial state `state` (one per next())."""
+    while True:
+        state = (state + _GAMMA) & _MASK64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        yield z ^ (z >> 31)
+
+
+def _iteration_stream(seed: int, k: int):
+    """Outputs k * 2**32 + 1, ... of the sequence seeded with `seed`: skip k * 2**32 increments."""
+    return splitmix64((seed + k * (1 << 32) * _GAMMA) & _MASK64)
+
+
+def _partial_shuffle(gen, n: int, m: int) -> list:
+    """m distinct indices of 0 .. n-1: the first m positions of a partial Fisher-Yates shuffle."""
+    moved = {}  # positions that no longer hold their own index
+    out = []
+    for j in range(m):
+        u = next(gen)
+        r = j + (((u >> 32) * (n - j)) >> 32)
+        vj, vr = moved.get(j, j), moved.get(r, r)
+        moved[j], moved[r] = vr, vj
+        out.append(moved[j])
+    return out
+
+
+def rows_generate(seed: int, start_iter: int, iters: int, M: int, B: int) -> np.ndarray:
+    """(iters, B) int32 table: the rows of iterations start_iter .. start_iter + iters - 1."""
+    if not 1 <= B <= M:
+        raise ValueError("need 1 <= B <= M")
+    return np.array([_partial_shuffle(_iteration_stream(seed, start_iter + i), M, B) for i in range(iters)],
+                    dtype=np.int32).reshape(iters, B)
+
+
+def subsets_generate(seed: int, start_iter: int, iters: int, F: int, T: int, R: int, nf: int, nt: int, nr: int):
+    """Per iteration: nf of F frequencies, then nt of T transmitters, then nr of R receivers from
+    the iteration's stream; three int32 tables (iters, nf), (iters, nt), (iters, nr)."""
+    fs, ts, rs = [], [], []
+    for i in range(iters):
+        gen = _iteration_stream(seed, start_iter + i)
+        fs.append(_partial_shuffle(gen, F, nf))
+        ts.append(_partial_shuffle(gen, T, nt))
+        rs.append(_partial_shuffle(gen, R, nr))
+    return (np.array(fs, dtype=np.int32).reshape(iters, nf), np.array(ts, dtype=np.int32).reshape(iters, nt),
+            np.array(rs, dtype=np.int32).reshape(iters, nr))

@@ -44,7 +44,8 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_solve_tol", "spgm_batch_options", "spgm_step_noalloc", "spgm_step_grad",
             "spgm_unrolled_vjp_step_g", "spgm_plan_launch_shape", "spgm_calibrate", "spgm_plan_autotune_batched",
             "spgm_plan_batched_shape", "spgm_plan_batched_candidates", "spgm_plan_autotune_structured",
-            "spgm_plan_structured_shape", "spgm_batch_autotune")
+            "spgm_plan_structured_shape", "spgm_batch_autotune", "spgm_rows_generate", "spgm_subsets_generate",
+            "spgm_solve_opts_init", "spgm_solve_ex")
 
 _dp = C.POINTER(C.c_double)
 
@@ -74,6 +75,14 @@ class SpgmError(RuntimeError):
 
 
 _LIB = None
+
+
+class SpgmSolveOpts(C.Structure):
+    """spgm_solve_opts (include/spgm.h)."""
+    _fields_ = [("iters", C.c_int32), ("B", C.c_int32), ("lam", C.c_double), ("eta", C.c_double),
+                ("rows_d", C.c_void_p), ("seed", C.c_uint64), ("sampling", C.c_int32), ("nf", C.c_int32),
+                ("nt", C.c_int32), ("nr", C.c_int32), ("start_iter", C.c_int32), ("tol", C.c_double),
+                ("check_every", C.c_int32), ("use_graph", C.c_int32), ("iters_done", C.POINTER(C.c_int32))]
 
 
 def load_library(path: str = LIB_PATH):
@@ -129,6 +138,11 @@ def load_library(path: str = LIB_PATH):
         "spgm_plan_autotune_structured": [vp, i32, i32, i32, C.c_char_p, C.POINTER(i32)],
         "spgm_plan_structured_shape": [vp, i32, i32, i32, C.POINTER(i32)],
         "spgm_batch_autotune": [vp, C.POINTER(i32), C.c_char_p, C.POINTER(i32)],
+        "spgm_rows_generate": [C.c_uint64, i32, i32, C.c_int64, i32, C.POINTER(i32)],
+        "spgm_subsets_generate": [C.c_uint64, i32, i32, i32, i32, i32, i32, i32, i32, C.POINTER(i32),
+                                  C.POINTER(i32), C.POINTER(i32)],
+        "spgm_solve_opts_init": [C.c_void_p],
+        "spgm_solve_ex": [vp, vp, vp, C.c_void_p, vp],
         "spgm_calibrate": [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "spgm_unrolled_vjp_step_g": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
         "spgm_solve_tol": [vp, vp, i32, i32, vp, vp, f32, f32, C.c_double, i32, i32, C.POINTER(i32),
@@ -189,6 +203,26 @@ def calibrate(kind, iters=4096):
     rate, ms = C.c_double(), C.c_double()
     _check(load_library().spgm_calibrate(int(kind), int(iters), C.byref(rate), C.byref(ms)))
     return rate.value, ms.value
+
+
+def rows_generate(seed, start_iter, iters, M, B):
+    """(iters, B) int32 rows of the library's seeded generator (host only)."""
+    out = np.empty((int(iters), int(B)), dtype=np.int32)
+    _check(load_library().spgm_rows_generate(C.c_uint64(int(seed) & (2 ** 64 - 1)), int(start_iter), int(iters),
+                                             int(M), int(B), out.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out
+
+
+def subsets_generate(seed, start_iter, iters, F, T, R, nf, nt, nr):
+    """(f (iters, nf), t (iters, nt), r (iters, nr)) int32 subsets of the seeded generator."""
+    f = np.empty((int(iters), int(nf)), dtype=np.int32)
+    t = np.empty((int(iters), int(nt)), dtype=np.int32)
+    r = np.empty((int(iters), int(nr)), dtype=np.int32)
+    ip = C.POINTER(C.c_int32)
+    _check(load_library().spgm_subsets_generate(C.c_uint64(int(seed) & (2 ** 64 - 1)), int(start_iter), int(iters),
+                                                int(F), int(T), int(R), int(nf), int(nt), int(nr),
+                                                f.ctypes.data_as(ip), t.ctypes.data_as(ip), r.ctypes.data_as(ip)))
+    return f, t, r
 
 
 def _stream_ptr(stream):
@@ -318,6 +352,24 @@ class Plan:
             raise err
         _check(rc)
         return done.value, changes[:done.value]
+
+    def spgm_solve_ex(self, y, s, iters, eta, lam, B=0, rows=None, seed=0, sampling=0, nf=0, nt=0, nr=0,
+                      start_iter=0, tol=0.0, check_every=50, use_graph=False, stream=None):
+        """spgm_solve_ex: rows (iters, B) on the device or None (seeded generator); returns the
+        number of iterations performed."""
+        import torch
+        o = SpgmSolveOpts()
+        _check(self._lib.spgm_solve_opts_init(C.byref(o)))
+        done = C.c_int32()
+        o.iters, o.lam, o.eta = int(iters), float(lam), float(eta)
+        o.B = int(B) if rows is None else int(rows.shape[1])
+        o.rows_d = None if rows is None else _dev(rows, torch.int32, "rows").value
+        o.seed, o.sampling, o.nf, o.nt, o.nr = int(seed) & (2 ** 64 - 1), int(sampling), int(nf), int(nt), int(nr)
+        o.start_iter, o.tol, o.check_every, o.use_graph = int(start_iter), float(tol), int(check_every), int(use_graph)
+        o.iters_done = C.pointer(done)
+        _check(self._lib.spgm_solve_ex(self._h, _dev(y, torch.complex64, "y", self.M),
+                                       _dev(s, torch.complex64, "s", self.N), C.byref(o), _stream_ptr(stream)))
+        return done.value
 
     # --- other regularisers: kind REG_L1, REG_ELASTIC_NET (mu) or REG_TV_MAGNITUDE (tv_iters) ---
     def spgm_prox(self, v, alpha, kind, mu=0.0, tv_iters=0, stream=None):

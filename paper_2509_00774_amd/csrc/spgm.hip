@@ -1354,6 +1354,13 @@ struct spgm_plan {
     std::map<int, std::array<int, 2>> mm_adj_tuned;
     // autotuned structured-minibatch kernels per (nf, nt, nr): items per thread (8 or 16)
     std::map<std::array<int, 3>, int> sf_tuned;
+    // minibatches drawn by the seeded generator: device rows (or subsets) of one chunk of
+    // iterations and two pinned host staging buffers with their copy-done events
+    int32_t *d_gen = nullptr;
+    size_t gen_cap = 0;
+    int32_t *h_gen[2] = {nullptr, nullptr};
+    size_t h_gen_cap = 0;
+    hipEvent_t gen_ev[2] = {nullptr, nullptr};
     // shared-geometry batches: packed right-hand sides [tile][z][8][2][64], forward partials
     // [brick run][row][32], packed residuals [row/8][2][64], adjoint partials [split][voxel][32]
     u32x4 *d_mm_s = nullptr;
@@ -1865,6 +1872,11 @@ int ensure_mm(spgm_plan *p, int B) {
         k_build_gtab<<<p->n_tiles, kThreads, p->lds_bytes>>>(p->geo, p->d_gtab);
         if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
             hipFree(p->d_gtab);
+    hipFree(p->d_gen);
+    for (int i = 0; i < 2; ++i) {
+        if (p->h_gen[i]) hipHostFree(p->h_gen[i]);
+        if (p->gen_ev[i]) hipEventDestroy(p->gen_ev[i]);
+    }
             p->d_gtab = nullptr;
             return fail(SPGM_E_DEVICE, "spgm: batched G-side table build failed");
         }
@@ -3091,6 +3103,190 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
     drop_graph(p);  // launch shapes changed
     if (fwd_out) *fwd_out = p->tuned[B].first.splits;
     if (adj_out) *adj_out = p->tuned[B].second.splits;
+    return ok();
+}
+
+// ------------------------------------------------------------------------------------------
+// Seeded minibatch generator.  SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom
+// number generators", OOPSLA 2014): the state advances by the golden-ratio increment and each
+// output is the new state through the published 64-bit finaliser.  Iteration k of a solve takes
+// outputs k 2^32 + 1, k 2^32 + 2, ... of the sequence seeded with `seed`, so its draws do not
+// depend on how the iterations are split over calls.  A partial Fisher-Yates shuffle of
+// 0 .. n-1 turns them into m distinct indices: draw j swaps position j with position
+// j + floor(hi32(u_j) (n - j) / 2^32) and index j is what position j then holds.
+// ------------------------------------------------------------------------------------------
+extern "C++" {
+struct SplitMix64 {
+    uint64_t state;
+    uint64_t next() {
+        state += 0x9E3779B97F4A7C15ull;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+};
+
+SplitMix64 iteration_stream(uint64_t seed, int64_t k) {
+    return SplitMix64{seed + (uint64_t)k * (0x9E3779B97F4A7C15ull << 32)};
+}
+
+// m distinct indices of 0 .. n-1 into out; perm holds the identity on entry and on return
+// (the positions a call swaps are reset, so a call costs O(m) however large n is).
+void fisher_yates(SplitMix64 &gen, int64_t n, int m, int32_t *out, std::vector<int32_t> &perm,
+                  std::vector<int64_t> &touched) {
+    touched.clear();
+    for (int j = 0; j < m; ++j) {
+        const uint64_t u = gen.next();
+        const int64_t r = j + (int64_t)(((u >> 32) * (uint64_t)(n - j)) >> 32);
+        std::swap(perm[j], perm[r]);
+        touched.push_back(r);
+        out[j] = perm[j];
+    }
+    for (int64_t r : touched) perm[r] = (int32_t)r;
+    for (int j = 0; j < m; ++j) perm[j] = j;
+}
+}  // extern "C++"
+
+int spgm_rows_generate(uint64_t seed, int32_t start_iter, int32_t iters, int64_t M, int32_t B, int32_t *rows) {
+    if (!rows || iters < 0 || start_iter < 0) return fail(SPGM_E_INVALID, "spgm_rows_generate: bad arguments");
+    if (M < 1 || M > INT32_MAX || B < 1 || B > M)
+        return fail(SPGM_E_INVALID, "spgm_rows_generate: need 1 <= B <= M < 2^31 (B=%d, M=%lld)", B, (long long)M);
+    std::vector<int32_t> perm(M);
+    for (int64_t i = 0; i < M; ++i) perm[i] = (int32_t)i;
+    std::vector<int64_t> touched;
+    for (int32_t i = 0; i < iters; ++i) {
+        SplitMix64 gen = iteration_stream(seed, (int64_t)start_iter + i);
+        fisher_yates(gen, M, B, rows + (size_t)i * B, perm, touched);
+    }
+    return ok();
+}
+
+int spgm_subsets_generate(uint64_t seed, int32_t start_iter, int32_t iters, int32_t F, int32_t T, int32_t R,
+                          int32_t nf, int32_t nt, int32_t nr, int32_t *f_idx, int32_t *t_idx, int32_t *r_idx) {
+    if (!f_idx || !t_idx || !r_idx || iters < 0 || start_iter < 0)
+        return fail(SPGM_E_INVALID, "spgm_subsets_generate: bad arguments");
+    if (nf < 1 || nf > F || nt < 1 || nt > T || nr < 1 || nr > R)
+        return fail(SPGM_E_INVALID, "spgm_subsets_generate: need 1 <= nf <= F, 1 <= nt <= T, 1 <= nr <= R");
+    std::vector<int32_t> pf(F), pt(T), pr(R);
+    for (int i = 0; i < F; ++i) pf[i] = i;
+    for (int i = 0; i < T; ++i) pt[i] = i;
+    for (int i = 0; i < R; ++i) pr[i] = i;
+    std::vector<int64_t> touched;
+    for (int32_t i = 0; i < iters; ++i) {
+        SplitMix64 gen = iteration_stream(seed, (int64_t)start_iter + i);
+        fisher_yates(gen, F, nf, f_idx + (size_t)i * nf, pf, touched);
+        fisher_yates(gen, T, nt, t_idx + (size_t)i * nt, pt, touched);
+        fisher_yates(gen, R, nr, r_idx + (size_t)i * nr, pr, touched);
+    }
+    return ok();
+}
+
+int spgm_solve_opts_init(spgm_solve_opts *o) {
+    if (!o) return fail(SPGM_E_INVALID, "spgm_solve_opts_init: opts is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->check_every = 50;
+    return ok();
+}
+
+extern "C++" {
+// Device buffer for `n` generated values and the two pinned staging buffers.
+static int gen_buffers(spgm_plan *p, size_t n) {
+    int rc;
+    if ((rc = grow_buf(p->d_gen, p->gen_cap, n))) return rc;
+    if (n > p->h_gen_cap) {
+        for (int i = 0; i < 2; ++i) {
+            if (p->gen_ev[i]) hipEventSynchronize(p->gen_ev[i]);
+            if (p->h_gen[i]) hipHostFree(p->h_gen[i]);
+            p->h_gen[i] = nullptr;
+        }
+        p->h_gen_cap = 0;
+        for (int i = 0; i < 2; ++i)
+            if (hipHostMalloc((void **)&p->h_gen[i], sizeof(int32_t) * n, hipHostMallocDefault) != hipSuccess)
+                return fail(SPGM_E_NOMEM, "spgm_solve_ex: pinned staging allocation failed");
+        p->h_gen_cap = n;
+    }
+    for (int i = 0; i < 2; ++i)
+        if (!p->gen_ev[i] && hipEventCreateWithFlags(&p->gen_ev[i], hipEventDisableTiming) != hipSuccess)
+            return fail(SPGM_E_NOMEM, "spgm_solve_ex: event creation failed");
+    return SPGM_OK;
+}
+}  // extern "C++"
+
+int spgm_solve_ex(spgm_plan *p, const void *y, void *s, const spgm_solve_opts *o, void *stream) {
+    if (!p || !o) return fail(SPGM_E_INVALID, "spgm_solve_ex: plan and opts must be non-NULL");
+    if (o->iters_done) *o->iters_done = 0;
+    if (o->iters < 0 || o->start_iter < 0) return fail(SPGM_E_INVALID, "spgm_solve_ex: iters and start_iter must be >= 0");
+    if (!(o->eta > 0.0) || !std::isfinite(o->eta) || !(o->lambda >= 0.0) || !std::isfinite(o->lambda))
+        return fail(SPGM_E_INVALID, "spgm_solve_ex: need eta > 0 and lambda >= 0, both finite");
+    if (o->sampling != 0 && o->sampling != 1) return fail(SPGM_E_INVALID, "spgm_solve_ex: unknown sampling %d", o->sampling);
+    const float eta = (float)o->eta, alpha = (float)(o->lambda * o->eta);
+    hipStream_t st = (hipStream_t)stream;
+    if (o->iters == 0) return ok();
+    DeviceGuard guard(p->device);
+    int rc;
+    if (o->sampling == 1) {
+        // structured minibatches from the generator: fixed iterations, eager launches
+        if (o->rows_d) return fail(SPGM_E_INVALID, "spgm_solve_ex: structured sampling draws its own subsets (rows_d must be NULL)");
+        if (o->tol > 0.0 || o->use_graph)
+            return fail(SPGM_E_UNSUPPORTED, "spgm_solve_ex: structured sampling runs fixed iterations without a graph");
+        const int nf = o->nf, nt = o->nt, nr = o->nr;
+        if (nf < 1 || nf > p->geo.F || nt < 1 || nt > p->geo.T || nr < 1 || nr > p->geo.R)
+            return fail(SPGM_E_INVALID, "spgm_solve_ex: need 1 <= nf <= F, 1 <= nt <= T, 1 <= nr <= R");
+        const int per = std::max(1, std::min(o->iters, (1 << 20) / (nf + nt + nr)));
+        if ((rc = gen_buffers(p, (size_t)per * (nf + nt + nr)))) return rc;
+        for (int i0 = 0, c = 0; i0 < o->iters; i0 += per, ++c) {
+            const int cnt = std::min(per, o->iters - i0);
+            int32_t *h = p->h_gen[c & 1];
+            if (hipEventSynchronize(p->gen_ev[c & 1]) != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_solve_ex: device error");
+            if ((rc = spgm_subsets_generate(o->seed, o->start_iter + i0, cnt, p->geo.F, p->geo.T, p->geo.R, nf, nt, nr,
+                                            h, h + (size_t)cnt * nf, h + (size_t)cnt * (nf + nt))))
+                return rc;
+            const size_t n = (size_t)cnt * (nf + nt + nr);
+            if (hipMemcpyAsync(p->d_gen, h, sizeof(int32_t) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipEventRecord(p->gen_ev[c & 1], st) != hipSuccess)
+                return fail(SPGM_E_DEVICE, "spgm_solve_ex: upload failed");
+            if ((rc = spgm_solve_structured(p, p->d_gen, nf, p->d_gen + (size_t)cnt * nf, nt,
+                                            p->d_gen + (size_t)cnt * (nf + nt), nr, cnt, y, s, eta, alpha, stream)))
+                return rc;
+            if (o->iters_done) *o->iters_done = i0 + cnt;
+        }
+        return ok();
+    }
+    const int B = o->B;
+    if (B < 1 || B > kMaxB) return fail(SPGM_E_INVALID, "spgm_solve_ex: B=%d outside [1, %d]", B, kMaxB);
+    auto run = [&](const int32_t *rows, int cnt, int *done) {
+        *done = cnt;
+        if (o->tol > 0.0)
+            return spgm_solve_tol(p, rows, cnt, B, y, s, eta, alpha, o->tol, std::max(1, o->check_every), o->use_graph,
+                                  done, nullptr, stream);
+        return o->use_graph ? spgm_solve_graph(p, rows, cnt, B, y, s, eta, alpha, stream)
+                            : spgm_solve(p, rows, cnt, B, y, s, eta, alpha, stream);
+    };
+    if (o->rows_d) {
+        int done = 0;
+        rc = run(o->rows_d, o->iters, &done);
+        if (o->iters_done) *o->iters_done = done;
+        return rc ? rc : ok();
+    }
+    if (B > p->M) return fail(SPGM_E_INVALID, "spgm_solve_ex: generated minibatches need B <= M (%d > %lld)", B, (long long)p->M);
+    const int per = std::max(1, std::min(o->iters, (1 << 22) / B));
+    if ((rc = gen_buffers(p, (size_t)per * B))) return rc;
+    for (int i0 = 0, c = 0; i0 < o->iters; i0 += per, ++c) {
+        const int cnt = std::min(per, o->iters - i0);
+        int32_t *h = p->h_gen[c & 1];
+        // the staging buffer's previous upload has finished before it is refilled
+        if (hipEventSynchronize(p->gen_ev[c & 1]) != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_solve_ex: device error");
+        if ((rc = spgm_rows_generate(o->seed, o->start_iter + i0, cnt, p->M, B, h))) return rc;
+        if (hipMemcpyAsync(p->d_gen, h, sizeof(int32_t) * (size_t)cnt * B, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipEventRecord(p->gen_ev[c & 1], st) != hipSuccess)
+            return fail(SPGM_E_DEVICE, "spgm_solve_ex: upload failed");
+        int done = 0;
+        rc = run(p->d_gen, cnt, &done);
+        if (o->iters_done) *o->iters_done = i0 + done;
+        if (rc) return rc;
+        if (done < cnt) break;  // termination rule met
+    }
     return ok();
 }
 
