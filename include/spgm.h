@@ -93,6 +93,22 @@ int spgm_phase_window(const spgm_geometry *geom, double *turns);
  * released by spgm_plan_destroy.  Synchronous. */
 int spgm_plan_create(spgm_plan **out, const spgm_geometry *geom, int32_t phase_mode);
 
+/* Options of spgm_plan_create_ex (spgm_plan_opts_init: phase_mode SPGM_PHASE_COMP32, device -1,
+ * tune_cache NULL). */
+typedef struct spgm_plan_opts {
+    int32_t phase_mode;     /* a spgm_phase_mode */
+    int32_t device;         /* HIP device ordinal the plan lives on; -1: the current device */
+    const char *tune_cache; /* default cache file of this plan's autotuners (copied; NULL: none, so
+                               the autotuners use SPGM_TUNE_CACHE) */
+} spgm_plan_opts;
+
+int spgm_plan_opts_init(spgm_plan_opts *opts);
+
+/* spgm_plan_create with options: creates the plan on opts->device (which must exist:
+ * SPGM_E_INVALID otherwise; the calling thread's current device is left as it was) and records
+ * the autotuner cache file.  Same geometry checks and errors as spgm_plan_create. */
+int spgm_plan_create_ex(spgm_plan **out, const spgm_geometry *geometry, const spgm_plan_opts *opts);
+
 /* Release a plan and its device memory (NULL is a no-op).  Synchronises the plan's device. */
 int spgm_plan_destroy(spgm_plan *plan);
 

@@ -45,7 +45,7 @@ EXPORTED = ("spgm_plan_create", "spgm_plan_destroy", "spgm_plan_dims", "spgm_for
             "spgm_unrolled_vjp_step_g", "spgm_plan_launch_shape", "spgm_calibrate", "spgm_plan_autotune_batched",
             "spgm_plan_batched_shape", "spgm_plan_batched_candidates", "spgm_plan_autotune_structured",
             "spgm_plan_structured_shape", "spgm_batch_autotune", "spgm_rows_generate", "spgm_subsets_generate",
-            "spgm_solve_opts_init", "spgm_solve_ex")
+            "spgm_solve_opts_init", "spgm_solve_ex", "spgm_plan_opts_init", "spgm_plan_create_ex")
 
 _dp = C.POINTER(C.c_double)
 
@@ -75,6 +75,11 @@ class SpgmError(RuntimeError):
 
 
 _LIB = None
+
+
+class SpgmPlanOpts(C.Structure):
+    """spgm_plan_opts (include/spgm.h)."""
+    _fields_ = [("phase_mode", C.c_int32), ("device", C.c_int32), ("tune_cache", C.c_char_p)]
 
 
 class SpgmSolveOpts(C.Structure):
@@ -143,6 +148,8 @@ def load_library(path: str = LIB_PATH):
                                   C.POINTER(i32), C.POINTER(i32)],
         "spgm_solve_opts_init": [C.c_void_p],
         "spgm_solve_ex": [vp, vp, vp, C.c_void_p, vp],
+        "spgm_plan_opts_init": [C.c_void_p],
+        "spgm_plan_create_ex": [C.POINTER(vp), C.c_void_p, C.c_void_p],
         "spgm_calibrate": [i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "spgm_unrolled_vjp_step_g": [vp, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp],
         "spgm_solve_tol": [vp, vp, i32, i32, vp, vp, f32, f32, C.c_double, i32, i32, C.POINTER(i32),
@@ -246,15 +253,24 @@ def _dev(t, dtype, name, numel=None):
 
 
 class Plan:
-    """A plan (``spgm_plan``) for one geometry on the current device."""
+    """A plan (``spgm_plan``) for one geometry on the current device (or on ``device``, with
+    ``tune_cache`` as its autotuners' default cache file: spgm_plan_create_ex)."""
 
-    def __init__(self, geom, phase_mode: int = PHASE_COMP32, _handle=None):
+    def __init__(self, geom, phase_mode: int = PHASE_COMP32, _handle=None, device=None, tune_cache=None):
         lib = load_library()
         self._owned = _handle is None
         if _handle is None:
             g, keep = make_geometry_struct(geom)
             h = C.c_void_p()
-            _check(lib.spgm_plan_create(C.byref(h), C.byref(g), int(phase_mode)))
+            if device is None and tune_cache is None:
+                _check(lib.spgm_plan_create(C.byref(h), C.byref(g), int(phase_mode)))
+            else:
+                o = SpgmPlanOpts()
+                _check(lib.spgm_plan_opts_init(C.byref(o)))
+                o.phase_mode = int(phase_mode)
+                o.device = -1 if device is None else int(device)
+                o.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+                _check(lib.spgm_plan_create_ex(C.byref(h), C.byref(g), C.byref(o)))
             del keep
         else:
             h = _handle

@@ -1354,6 +1354,8 @@ struct spgm_plan {
     std::map<int, std::array<int, 2>> mm_adj_tuned;
     // autotuned structured-minibatch kernels per (nf, nt, nr): items per thread (8 or 16)
     std::map<std::array<int, 3>, int> sf_tuned;
+    // default autotuner cache file of this plan (spgm_plan_create_ex; empty: SPGM_TUNE_CACHE)
+    std::string tune_cache;
     // minibatches drawn by the seeded generator: device rows (or subsets) of one chunk of
     // iterations and two pinned host staging buffers with their copy-done events
     int32_t *d_gen = nullptr;
@@ -2348,6 +2350,30 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
     return ok();
 }
 
+int spgm_plan_opts_init(spgm_plan_opts *o) {
+    if (!o) return fail(SPGM_E_INVALID, "spgm_plan_opts_init: opts is NULL");
+    o->phase_mode = SPGM_PHASE_COMP32;
+    o->device = -1;
+    o->tune_cache = nullptr;
+    return ok();
+}
+
+int spgm_plan_create_ex(spgm_plan **out, const spgm_geometry *gm, const spgm_plan_opts *o) {
+    if (!o) return fail(SPGM_E_INVALID, "spgm_plan_create_ex: opts is NULL");
+    int rc;
+    if (o->device >= 0) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || o->device >= n)
+            return fail(SPGM_E_INVALID, "spgm_plan_create_ex: device %d is not present", o->device);
+        DeviceGuard guard(o->device);
+        rc = spgm_plan_create(out, gm, o->phase_mode);
+    } else {
+        rc = spgm_plan_create(out, gm, o->phase_mode);
+    }
+    if (rc == SPGM_OK && o->tune_cache) (*out)->tune_cache = o->tune_cache;
+    return rc;
+}
+
 int spgm_plan_destroy(spgm_plan *p) {
     if (!p) return ok();
     DeviceGuard guard(p->device);
@@ -2995,7 +3021,7 @@ int spgm_plan_autotune(spgm_plan *p, int32_t B, const char *cache_path, int32_t 
     // The timing runs on a stream of its own and rewrites the plan's workspace: work queued
     // earlier on any stream may still use it.
     if (hipDeviceSynchronize() != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_autotune: device error");
-    std::string path = cache_path ? cache_path : "";
+    std::string path = cache_path ? cache_path : p->tune_cache;
     if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
     const std::string key = tune_key(p, B);
     std::map<std::string, std::vector<double>> cache;
@@ -3392,7 +3418,7 @@ int spgm_plan_autotune_batched(spgm_plan *p, int32_t B, int32_t prec, const char
         return fail(SPGM_E_UNSUPPORTED, "spgm_plan_autotune_batched: needs a plan created with SPGM_PHASE_COMP32");
     DeviceGuard guard(p->device);
     if (hipDeviceSynchronize() != hipSuccess) return fail(SPGM_E_DEVICE, "spgm_plan_autotune_batched: device error");
-    std::string path = cache_path ? cache_path : "";
+    std::string path = cache_path ? cache_path : p->tune_cache;
     if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
     const std::string key = tune_key(p, B) + "|mm" + std::to_string(prec);
     std::map<std::string, std::vector<double>> cache;
@@ -3517,7 +3543,7 @@ int spgm_plan_autotune_structured(spgm_plan *p, int32_t nf, int32_t nt, int32_t 
     }
     const SFArgs a{d_idx, d_idx, d_idx, nf, nt, nr, nf * nt * nr};
     int rc = sf_check(p, a, "spgm_plan_autotune_structured");
-    std::string path = cache_path ? cache_path : "";
+    std::string path = cache_path ? cache_path : p->tune_cache;
     if (path.empty() && std::getenv("SPGM_TUNE_CACHE")) path = std::getenv("SPGM_TUNE_CACHE");
     std::ostringstream ks;
     ks << tune_key(p, a.B) << "|sf|nf" << nf << "|nt" << nt << "|nr" << nr;

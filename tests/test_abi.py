@@ -140,3 +140,26 @@ def test_compensated_plan_refused_beyond_the_window(lib):
     assert rc != bd.SPGM_E_UNSUPPORTED
     if rc == bd.SPGM_OK:
         lib.spgm_plan_destroy(h)
+
+
+def test_plan_create_ex_rejects_bad_options(lib):
+    geom = W.make_geometry(4, 5, 3, (20e9, 30e9), (4, 4, 4), 5e-3, 0.25, 0.2, seed=1)
+    g, keep = bd.make_geometry_struct(geom)
+    h = C.c_void_p()
+    assert lib.spgm_plan_create_ex(C.byref(h), C.byref(g), None) == bd.SPGM_E_INVALID
+    o = bd.SpgmPlanOpts()
+    assert lib.spgm_plan_opts_init(C.byref(o)) == bd.SPGM_OK
+    assert (o.phase_mode, o.device, o.tune_cache) == (bd.PHASE_COMP32, -1, None)
+    o.phase_mode = 9
+    assert lib.spgm_plan_create_ex(C.byref(h), C.byref(g), C.byref(o)) == bd.SPGM_E_INVALID
+    o.phase_mode = bd.PHASE_COMP32
+    o.device = 1 << 20  # no such device (and none at all without a GPU)
+    assert lib.spgm_plan_create_ex(C.byref(h), C.byref(g), C.byref(o)) == bd.SPGM_E_INVALID
+    assert b"not present" in lib.spgm_last_error()
+
+
+def test_solve_opts_defaults(lib):
+    o = bd.SpgmSolveOpts()
+    assert lib.spgm_solve_opts_init(C.byref(o)) == bd.SPGM_OK
+    assert o.check_every == 50 and o.iters == 0 and o.B == 0 and not o.rows_d and o.tol == 0.0
+    assert lib.spgm_solve_ex(None, None, None, C.byref(o), None) == bd.SPGM_E_INVALID

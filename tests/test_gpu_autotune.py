@@ -232,3 +232,17 @@ def test_ragged_batch_every_candidate(bd, tmp_path):
             print("[autotune-batch] rows per item %d scene %d: rel_l2 %.2e" % (rps, i, err), flush=True)
             assert err <= 1e-5
         batch.close()
+
+
+def test_plan_options_device_and_cache(bd, tmp_path):
+    """A plan made with spgm_plan_create_ex on device 0 with a cache file: its autotuners write
+    to that file when given no path."""
+    geom = W.config_geometry("c0")
+    cache = tmp_path / "plan_cache.json"
+    plan = bd.Plan(geom, device=0, tune_cache=str(cache))
+    fs, as_ = plan.autotune(256)
+    shape = plan.spgm_plan_autotune_batched(256)
+    keys = list(json.load(open(cache)).keys())
+    assert len(keys) == 2 and any(k.endswith("|mm0") for k in keys)
+    assert plan.spgm_plan_launch_shape(256)[0][0] == fs and plan.spgm_plan_batched_shape(256) == shape
+    plan.close()
