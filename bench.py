@@ -738,7 +738,8 @@ def bench_batched(args, torch, binding, dev):
     log("NMSE vs truth after %d iterations: batched bf16 mean %.3f dB, float32 mean %.3f dB, worst gap %.4f dB; "
         "float32 solves of the %d scenes one by one: %.3f s" % (steps, np.mean(nmse_b), np.mean(nmse_f), dnmse, Kr, t_f))
     flops = 8.0 * entries * Kr  # real flops of one batched operator
-    kname, kavg = ("k_mm_fwd", fwd_avg) if fwd_avg >= adj_avg else ("k_mm_adj", adj_avg)
+    fwd_name = "k_mm_fwd_rows" if shape[6] else "k_mm_fwd"  # entries in A-operand order or via LDS
+    kname, kavg = (fwd_name, fwd_avg) if fwd_avg >= adj_avg else ("k_mm_adj", adj_avg)
     achieved = flops / kavg
     cpu = None
     rel = None
