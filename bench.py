@@ -71,13 +71,25 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
+def mm_shape_key(shape):
+    """Key of a batched launch shape (spgm_plan_batched_shape's first six values)."""
+    return "shape" + "x".join(str(int(v)) for v in shape[:6])
+
+
 def stored_traffic(kernel, workload, shape=None):
-    """HBM bytes per launch from the committed counter runs (per launch shape, row splits and
-    waves per work-group, for the tile kernels), if the kernel source is unchanged."""
+    """HBM bytes per launch from the committed counter runs (per launch shape: row splits and
+    waves per work-group for the tile kernels, a mm_shape_key string for the batched kernels),
+    if the kernel source is unchanged."""
     if not os.path.exists(TRAFFIC):
         return None
     data = json.load(open(TRAFFIC))
-    key = "%s/%s" % (kernel, workload) + ("/splits%d/waves%d" % tuple(shape) if shape else "")
+    if shape is None:
+        suffix = ""
+    elif isinstance(shape, str):
+        suffix = "/" + shape
+    else:
+        suffix = "/splits%d/waves%d" % tuple(shape)
+    key = "%s/%s" % (kernel, workload) + suffix
     rec = data.get(key)
     if not rec or rec.get("source_sha") != source_sha():
         return None
@@ -779,7 +791,7 @@ def bench_batched(args, torch, binding, dev):
         "rel_l2_vs_oracle_after_1_iter": None if rel is None else float("%.3e" % rel),
         "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved / 1e12, 2),
                      "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK, 4),
-                     "traffic": stored_traffic(kname, "c1k32"), "flops_per_launch": flops,
+                     "traffic": stored_traffic(kname, "c1k32", mm_shape_key(shape)), "flops_per_launch": flops,
                      "avg_launch_ms": round(kavg * 1e3, 5),
                      "fwd_mm_ms": round(fwd_avg * 1e3, 5), "adj_mm_ms": round(adj_avg * 1e3, 5),
                      "fwd_gentries_per_s": round(entries / fwd_avg / 1e9, 1),
@@ -883,7 +895,7 @@ def bench_structured(args, torch, binding, dev):
         "rel_l2_vs_oracle_after_iters": n_par,
         "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved / 1e12, 3),
                      "peak": 157.3, "unit": "TFLOP/s (float32 matrix cores)", "frac": round(achieved / 157.3e12, 4),
-                     "traffic": stored_traffic(kname, "c1s"), "flops_per_launch": flops,
+                     "traffic": stored_traffic(kname, "c1s", "items%d" % items), "flops_per_launch": flops,
                      "avg_launch_ms": round(kavg * 1e3, 5),
                      "sf_fwd_ms": round(fwd_avg * 1e3, 5), "sf_adj_ms": round(adj_avg * 1e3, 5),
                      "factors_per_launch": nf * (nt + nr) * N},

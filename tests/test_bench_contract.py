@@ -35,6 +35,12 @@ def test_traffic_record_needs_matching_source_and_split(tmp_path, monkeypatch):
     assert bench.stored_traffic("k_fwd_tile", "c1", (4, 16)) is None  # other waves per work-group
     assert bench.stored_traffic("k_fwd_tile", "c1") is None     # tile kernels are keyed by launch shape
     assert bench.stored_traffic("k_row_reduce", "c1") == 789
+    key = bench.mm_shape_key((4, 8, 8, 4, 1, 1024, 1))
+    assert key == "shape4x8x8x4x1x1024"
+    data["k_mm_adj/c1k32/" + key] = {"source_sha": sha, "bytes_per_launch": 55}
+    path.write_text(json.dumps(data))
+    assert bench.stored_traffic("k_mm_adj", "c1k32", key) == 55
+    assert bench.stored_traffic("k_mm_adj", "c1k32", bench.mm_shape_key((2, 8, 8, 4, 1, 1024))) is None
     monkeypatch.setattr(bench, "TRAFFIC", str(tmp_path / "missing.json"))
     assert bench.stored_traffic("k_row_reduce", "c1") is None
 
@@ -46,6 +52,8 @@ def test_committed_traffic_records_name_their_split_and_source():
         if kernel in ("k_fwd_tile", "k_adj_tile"):
             parts = key.split("/")
             assert parts[2].startswith("splits") and parts[3].startswith("waves"), key
+        if kernel in ("k_mm_fwd", "k_mm_fwd_rows", "k_mm_adj"):
+            assert key.split("/")[2].startswith("shape"), key
         assert len(rec["source_sha"]) == 16
         # read + write, each rounded down separately
         assert abs(rec["bytes_per_launch"] - rec["read_bytes"] - rec["write_bytes"]) <= 1
