@@ -313,8 +313,9 @@ int spgm_plan_batched_candidates(const spgm_plan *plan, int32_t B, int32_t *fwd,
                                  int32_t *adj, int32_t adj_cap, int32_t *n_adj);
 
 /* Autotuner of the structured-minibatch kernels for subsets of nf frequencies, nt transmitters
- * and nr receivers: times the small-register instances (8 items per thread; only for
- * nt + nr <= 32 and nt <= 16) against the general ones (16 items) on the forward and adjoint
+ * and nr receivers: times the small-register instances (8 items per thread and 128 voxels, two
+ * work-groups per compute unit; only for nt + nr <= 32 and nt <= 16) against the general ones
+ * (16 items, one work-group per compute unit) on the forward and adjoint
  * kernels, and keeps the faster for every later structured call of this plan with this
  * (nf, nt, nr).  Cached like spgm_plan_autotune (key plus "|sf|nf..|nt..|nr..", value
  * [items, ms]).  *items (required) receives the applied choice.  Synchronous; waits for all work
@@ -323,8 +324,8 @@ int spgm_plan_batched_candidates(const spgm_plan *plan, int32_t B, int32_t *fwd,
 int spgm_plan_autotune_structured(spgm_plan *plan, int32_t nf, int32_t nt, int32_t nr, const char *cache_path,
                                   int32_t *items);
 
-/* Items per thread (8 or 16) the structured kernels use for (nf, nt, nr) on this plan.  Host
- * only. */
+/* Items per thread and 128 voxels (8 or 16) of the structured kernel instances used for
+ * (nf, nt, nr) on this plan.  Host only. */
 int spgm_plan_structured_shape(const spgm_plan *plan, int32_t nf, int32_t nt, int32_t nr, int32_t *items);
 
 /* Launch shape the tile kernels use for minibatches of B rows on this plan (the autotuned one,

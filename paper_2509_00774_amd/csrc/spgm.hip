@@ -2095,10 +2095,10 @@ int sf_adjoint_partials(spgm_plan *p, const SFArgs &a, hipStream_t st) {
     if (ev) hipEventRecord(ev[0], st);
     const size_t lds = sf_lds_bytes(p->geo.T + p->geo.R);
     if (sf_small(p, a))
-        k_sf_adj<kSFItemsSmall, 2><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr,
+        k_sf_adj<kSFItemsSmall, 1><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr,
                                                                       p->d_rs, p->d_gpart, (int)p->N);
     else
-        k_sf_adj<kSFItems, 4><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr, p->d_rs,
+        k_sf_adj<kSFItems, 2><<<p->n_tiles, kThreads, lds, st>>>(p->geo, a.fi, a.nf, a.ti, a.nt, a.ri, a.nr, p->d_rs,
                                                                  p->d_gpart, (int)p->N);
     if (ev) hipEventRecord(ev[1], st);
     return launch_check("structured adjoint");
@@ -2341,7 +2341,7 @@ int spgm_plan_create(spgm_plan **out, const spgm_geometry *gm, int32_t phase_mod
         (const void *)k_mm_fwd_rows<SPGM_MM_FP16, 3>, (const void *)k_mm_fwd_rows<SPGM_MM_FP16, 4>};
     for (const void *k : mm_rows_kernels) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     const void *sf_kernels[] = {(const void *)k_sf_fwd<kSFItemsSmall>, (const void *)k_sf_fwd<kSFItems>,
-                                (const void *)k_sf_adj<kSFItemsSmall, 2>, (const void *)k_sf_adj<kSFItems, 4>};
+                                (const void *)k_sf_adj<kSFItemsSmall, 1>, (const void *)k_sf_adj<kSFItems, 2>};
     for (const void *k : sf_kernels)
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sf_lds_bytes((int)A));
     hipGetLastError();
