@@ -483,9 +483,9 @@ int spgm_batch_solve(spgm_batch *batch, int32_t iters, const int32_t *B, const i
 int spgm_batch_options(spgm_batch *batch, int32_t max_workgroups, int32_t rows_per_split);
 
 /* Autotuner of the ragged batch: for minibatch sizes B[0..n-1] (one per scene, host array),
- * times one SPGM iteration of the batch with 256, 512, 1024, 2048 and 4096 rows per work item
- * (the row split of every scene; spgm_batch_options' rows_per_split) on pseudo-random rows and
- * keeps the fastest for the batch.  Cached like spgm_plan_autotune (key: architecture, phase
+ * times one SPGM iteration of the batch with 256, 512, 1024, 2048, 4096, 8192 and 16384 rows
+ * per work item (the row split of every scene; spgm_batch_options' rows_per_split) on
+ * pseudo-random rows and keeps the fastest for the batch.  Cached like spgm_plan_autotune (key: architecture, phase
  * mode, number of scenes and a hash of every scene's T, R, F, grid and B; value [rows per work
  * item, ms]); a cached key is applied without timing.  *rows_per_split (optional) receives the
  * applied value.  Synchronous; waits for all work on the batch's device first; allocates

@@ -3895,7 +3895,7 @@ int spgm_plan_launch_shape(const spgm_plan *p, int32_t B, int32_t *fwd_splits, i
 }
 
 // Autotuner of the ragged batch: rows per work item (the row split of every scene) among 256,
-// 512, 1024, 2048 and 4096, timed on one SPGM iteration over pseudo-random rows of the given
+// 512, ..., 16384 (powers of two), timed on one SPGM iteration over pseudo-random rows of the given
 // minibatch sizes; cached in the same file, keyed by architecture, phase mode and a hash of
 // every scene's (T, R, F, grid, B).
 int spgm_batch_autotune(spgm_batch *b, const int32_t *B, const char *cache_path, int32_t *rows_per_split) {
@@ -3964,7 +3964,7 @@ int spgm_batch_autotune(spgm_batch *b, const int32_t *B, const char *cache_path,
         b->max_wg = 0;
         double best = 1e30;
         int best_r = kBatchRowsPerSplit;
-        for (int r : {256, 512, 1024, 2048, 4096}) {
+        for (int r : {256, 512, 1024, 2048, 4096, 8192, 16384}) {
             if (rc) break;
             b->rows_per_split = r;
             float tbest = 1e30f;

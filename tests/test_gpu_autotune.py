@@ -217,9 +217,9 @@ def test_ragged_batch_every_candidate(bd, tmp_path):
         refs.append(orc.solve(rows[i], ys[i].astype(np.complex128), s64, etas[i], alphas[i]))
     cache = tmp_path / "tune.json"
     chosen = bd.Batch(geoms).autotune(Bs, str(cache))
-    assert chosen in (256, 512, 1024, 2048, 4096)
+    assert chosen in (256, 512, 1024, 2048, 4096, 8192, 16384)
     key = [k for k in json.load(open(cache)) if "|batch|" in k][0]
-    for rps in (256, 512, 1024, 2048, 4096):
+    for rps in (256, 512, 1024, 2048, 4096, 8192, 16384):
         json.dump({key: [rps]}, open(cache, "w"))
         batch = bd.Batch(geoms)
         assert batch.autotune(Bs, str(cache)) == rps
