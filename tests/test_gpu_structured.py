@@ -90,9 +90,9 @@ def test_c0_structured_projector(bd, nf, nt, nr):
     (9, 3, 4, (8, 8, 4), 1, 1, 1),        # a single row
     (2, 1, 1, (3, 2, 1), 1, 2, 1),        # smallest grid
     (16, 9, 11, (17, 9, 12), 11, 16, 9),  # every row of the matrix (M = 1584)
-    (20, 24, 3, (8, 8, 4), 2, 16, 20),    # 1 x 3 output tiles (one wave idle)
-    (20, 12, 3, (8, 8, 4), 2, 17, 9),     # 2 x 2 output tiles (one per wave)
-    (24, 24, 3, (8, 8, 4), 2, 20, 24),    # 2 x 3 output tiles (two for some waves)
+    (20, 24, 3, (8, 8, 4), 2, 16, 20),    # 1 x 3 output tiles (two waves each, two idle)
+    (20, 12, 3, (8, 8, 4), 2, 17, 9),     # 2 x 2 output tiles (two waves each)
+    (24, 24, 3, (8, 8, 4), 2, 20, 24),    # 2 x 3 output tiles (one wave each, two idle)
 ])
 def test_structured_ragged_shapes(bd, T, R, F, grid, nf, nt, nr):
     pulse = np.exp(1j * np.linspace(0, 2, F)) * np.linspace(1.0, 0.4, F)
